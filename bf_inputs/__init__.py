@@ -20,15 +20,44 @@ from __future__ import annotations
 import numpy as np
 
 
-def complex_gaussian(shape, seed, dtype=np.complex128):
-    """iid standard complex Gaussian entries (a + i b)/sqrt(2), a, b ~ N(0, 1)."""
-    rng = np.random.default_rng(seed)
-    a = rng.standard_normal(shape)
-    b = rng.standard_normal(shape)
+_CHUNK = 1 << 22          # doubles per independently seeded chunk
+
+
+def _fill_normal(flat, seed, threads=None, scale=1.0):
+    """Fill a float64 array with scale * N(0,1) draws, chunk k seeded by (seed, k).
+
+    The values depend only on `seed` and the array length, not on the number
+    of threads used to produce them.
+    """
+    import concurrent.futures as cf
+    import os
+    n = flat.size
+    nchunk = (n + _CHUNK - 1) // _CHUNK
+    ss = seed if isinstance(seed, np.random.SeedSequence) else np.random.SeedSequence(seed)
+
+    def work(k):
+        child = np.random.SeedSequence(ss.entropy, spawn_key=tuple(ss.spawn_key) + (k,))
+        rng = np.random.default_rng(child)
+        part = flat[k * _CHUNK:min(n, (k + 1) * _CHUNK)]
+        rng.standard_normal(out=part)
+        if scale != 1.0:
+            part *= scale
+
+    if threads is None:
+        threads = min(16, os.cpu_count() or 1)
+    if nchunk == 1 or threads == 1:
+        for k in range(nchunk):
+            work(k)
+    else:
+        with cf.ThreadPoolExecutor(threads) as ex:
+            list(ex.map(work, range(nchunk)))
+
+
+def complex_gaussian(shape, seed, dtype=np.complex128, scale=1.0):
+    """iid complex Gaussian entries (a + i b) * scale / sqrt(2), a, b ~ N(0, 1)."""
     out = np.empty(shape, dtype=np.complex128)
-    out.real = a
-    out.imag = b
-    out *= np.sqrt(0.5)
+    flat = out.reshape(-1).view(np.float64)
+    _fill_normal(flat, seed, scale=scale * np.sqrt(0.5))
     return out.astype(dtype, copy=False)
 
 
@@ -70,15 +99,15 @@ def synthetic_factors(radix, leaf, L, r, seed, s_range=(0.25, 4.0)):
     kids = ss.spawn(4 + 2 * len(shapes["H"]))
     f = {
         "radix": R, "leaf": n0, "L": int(L), "r": int(r),
-        "VL": complex_gaussian(shapes["VL"], kids[0]) / np.sqrt(n0),
-        "UL": complex_gaussian(shapes["UL"], kids[1]) / np.sqrt(r),
+        "VL": complex_gaussian(shapes["VL"], kids[0], scale=1.0 / np.sqrt(n0)),
+        "UL": complex_gaussian(shapes["UL"], kids[1], scale=1.0 / np.sqrt(r)),
     }
     lo, hi = np.log(s_range[0]), np.log(s_range[1])
     f["S"] = np.exp(np.random.default_rng(kids[2]).uniform(lo, hi, shapes["S"]))
     scale = 1.0 / np.sqrt(R * r)
-    f["H"] = [complex_gaussian(s, kids[4 + t]) * scale
+    f["H"] = [complex_gaussian(s, kids[4 + t], scale=scale)
               for t, s in enumerate(shapes["H"])]
-    f["G"] = [complex_gaussian(s, kids[4 + len(shapes["H"]) + t]) * scale
+    f["G"] = [complex_gaussian(s, kids[4 + len(shapes["H"]) + t], scale=scale)
               for t, s in enumerate(shapes["G"])]
     return f
 

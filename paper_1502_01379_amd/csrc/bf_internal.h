@@ -1,0 +1,108 @@
+// Internal declarations shared by the host side and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "bf.h"
+
+namespace bfly {
+
+// Activation layout used by every kernel between launches: right-hand sides are
+// grouped in chunks of 32 (one chunk per wavefront of the fused kernels), and a
+// chunk holds, for every slot, r rows of 32 interleaved complex values:
+//   element (slot, row, n) -> ((n / 32) * nslots + slot) * r * 32 + row * 32 + n % 32
+// nslots = R^L at every level of the tree (R^l nodes of one tree times R^(L-l)
+// nodes of the other).
+constexpr int kChunk = 32;
+
+inline int64_t act_elems(int64_t nslots, int r, int64_t nchunks) {
+  return nchunks * nslots * r * kChunk;
+}
+
+// Slot patterns of one butterfly level.  Butterfly b = hi * blo + lo combines R
+// input slots and produces R output slots:
+//   strided(b, c)    = hi * R * blo + c * blo + lo
+//   contiguous(b, c) = hi * R * blo + R * lo + c
+// H-side forward and G-side adjoint levels read strided and write contiguous
+// slots; G-side forward and H-side adjoint levels do the opposite.
+enum SlotMode : int { kStridedIn = 0, kContigIn = 1 };
+
+// One step of the factor product as the per-level kernels see it.
+struct LevelOp {
+  enum Kind : int { kLeafIn, kButterfly, kMiddle, kLeafOut } kind;
+  SlotMode mode = kStridedIn;
+  int64_t nb = 0;    // butterflies (kButterfly)
+  int64_t blo = 0;   // see SlotMode
+  bool tconj = false; // butterfly: conjugate-transposed blocks; middle: transposed S
+  const void *mat = nullptr;  // canonical factor array of this op (device)
+  std::string name;
+};
+
+struct FusedPass;  // fused MFMA pass description (bf_fused.hip)
+
+struct ProfRec {
+  std::string name;
+  hipEvent_t start, stop;
+};
+
+}  // namespace bfly
+
+struct bf_plan {
+  bf_shape shape{};
+  bf_precision prec = BF_PREC_F32;
+  int path = 0;  // 0 = per-level kernels, 1 = fused MFMA passes
+  int R = 2, n0 = 0, L = 0, r = 0, h = 0;
+  int64_t P = 0, m = 0, N = 0;
+
+  // device memory owned by the plan
+  std::vector<void *> allocs;
+  // per-level path: forward and adjoint op lists
+  std::vector<bfly::LevelOp> fwd_ops, adj_ops;
+  // fused path
+  std::vector<bfly::FusedPass *> fwd_passes, adj_passes;
+  // middle weights, FP32 or FP64 by precision: S[i][j][k] and its transpose
+  void *S = nullptr, *ST = nullptr;
+
+  // workspace: ping-pong activation buffers plus per-level storage for backward
+  void *ws = nullptr;
+  size_t ws_bytes = 0;
+
+  std::string err;
+  bool profiling = false;
+  std::vector<bfly::ProfRec> prof_pending;
+  std::vector<hipEvent_t> event_pool;
+  std::vector<std::string> prof_names;
+  std::vector<double> prof_ms;
+  std::vector<int64_t> prof_launches;
+
+  ~bf_plan();
+};
+
+namespace bfly {
+
+// Launch helpers (bf_simple.hip)
+hipError_t launch_level_op(const bf_plan *p, const LevelOp &op, const void *in, int64_t ld_in,
+                           void *out, int64_t ld_out, int64_t nrhs, hipStream_t s);
+hipError_t launch_level_grad(const bf_plan *p, const LevelOp &op, const void *X, const void *Y,
+                             void *grad, int64_t nrhs, hipStream_t s);
+hipError_t launch_leaf_grad(const bf_plan *p, const void *user, int64_t ld, const void *act,
+                            void *grad, int64_t nrhs, hipStream_t s);
+hipError_t launch_middle_grad(const bf_plan *p, const void *dz, const void *y, void *grad,
+                              int64_t nrhs, hipStream_t s);
+
+// Fused path (bf_fused.hip)
+bool fused_supported(const bf_shape &sh, bf_precision prec);
+bf_status fused_build(bf_plan *p, const bf_factors_host *f);
+hipError_t fused_run(bf_plan *p, bool adjoint, const void *g, void *u, int64_t nrhs, int64_t ld,
+                     void *buf0, void *buf1, hipStream_t s);
+void fused_free(FusedPass *fp);
+
+// Profiling hooks (bf_api.hip)
+void prof_begin(bf_plan *p, const std::string &name, hipStream_t s);
+void prof_end(bf_plan *p, hipStream_t s);
+
+}  // namespace bfly

@@ -1,0 +1,313 @@
+// Per-level kernels: one launch per factor of the product, any radix, rank and
+// leaf size, FP64 or FP32.  These run the FP64 path, every shape the fused MFMA
+// passes do not cover, and the per-level steps of the backward pass.
+//
+// Each factor is one of
+//   leaf-in     y_j = W_j^* x_{leaf j}       W = V^L_j forward, U^L_j adjoint
+//   butterfly   out[c_out r + a] = sum_k M_b[c_out r + a][k] in[k],  k = c_in r + b
+//               (the R x R block relation of one butterfly, Sec. 3.2.1 / 3.2.2)
+//   middle      y[(a m + b)] = S[a][b] .* x[(b m + a)]    (Sec. 3.1, M^h)
+//   leaf-out    u_{leaf i} = W_i z_i          W = U^L_i forward, V^L_i adjoint
+// Factors are read in the canonical layout of bf.h, converted to the compute
+// precision, without any repacking.
+#include <hip/hip_runtime.h>
+
+#include "bf_internal.h"
+
+namespace bfly {
+namespace {
+
+template <class T> struct Cx;
+template <> struct Cx<float> { using type = float2; };
+template <> struct Cx<double> { using type = double2; };
+
+template <class C> __device__ __forceinline__ C cmul(C a, C b) {
+  C o;
+  o.x = a.x * b.x - a.y * b.y;
+  o.y = a.x * b.y + a.y * b.x;
+  return o;
+}
+// a * conj(b)
+template <class C> __device__ __forceinline__ C cmulc(C a, C b) {
+  C o;
+  o.x = a.x * b.x + a.y * b.y;
+  o.y = a.y * b.x - a.x * b.y;
+  return o;
+}
+
+__device__ __forceinline__ int64_t act_off(int64_t slot, int row, int64_t n, int64_t nslots, int r) {
+  return (((n >> 5) * nslots + slot) * r + row) * kChunk + (n & 31);
+}
+
+__device__ __forceinline__ int64_t slot_of(int64_t b, int c, int64_t blo, int R, bool strided) {
+  const int64_t hi = b / blo, lo = b - hi * blo;
+  return strided ? hi * R * blo + c * blo + lo : hi * R * blo + R * lo + c;
+}
+
+// y[j][a][n] = sum_p conj(W[j][p][a]) x[(j n0 + p) ld + n] with W the canonical
+// [P][n0][r] leaf array (V^L forward, U^L adjoint); padded columns get zeros.
+template <class T>
+__global__ void k_leaf_in(const typename Cx<T>::type *__restrict__ W,
+                          const typename Cx<T>::type *__restrict__ x, int64_t ld,
+                          typename Cx<T>::type *__restrict__ y, int64_t P, int n0, int r,
+                          int64_t nrhs, int64_t npad) {
+  using C = typename Cx<T>::type;
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= P * r * npad) return;
+  const int64_t n = t % npad;
+  const int a = (int)((t / npad) % r);
+  const int64_t j = t / (npad * r);
+  C acc{0, 0};
+  if (n < nrhs) {
+    const C *w = W + j * n0 * r + a;
+    for (int p = 0; p < n0; ++p) {
+      const C v = x[(j * n0 + p) * ld + n];
+      const C c = cmulc(v, w[p * r]);
+      acc.x += c.x;
+      acc.y += c.y;
+    }
+  }
+  y[act_off(j, a, n, P, r)] = acc;
+}
+
+// u[(i n0 + p) ld + n] = sum_a W[i][p][a] z[i][a][n]
+template <class T>
+__global__ void k_leaf_out(const typename Cx<T>::type *__restrict__ W,
+                           const typename Cx<T>::type *__restrict__ z,
+                           typename Cx<T>::type *__restrict__ u, int64_t ld, int64_t P, int n0,
+                           int r, int64_t nrhs) {
+  using C = typename Cx<T>::type;
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= P * n0 * nrhs) return;
+  const int64_t n = t % nrhs;
+  const int p = (int)((t / nrhs) % n0);
+  const int64_t i = t / (nrhs * n0);
+  const C *w = W + (i * n0 + p) * r;
+  C acc{0, 0};
+  for (int a = 0; a < r; ++a) {
+    const C c = cmul(w[a], z[act_off(i, a, n, P, r)]);
+    acc.x += c.x;
+    acc.y += c.y;
+  }
+  u[(i * n0 + p) * ld + n] = acc;
+}
+
+// One butterfly level: thread per (butterfly, output row, column).  Fb is the
+// canonical level array [R^(l+1)][blo][r][R r].  With o = c_out r + a_out and
+// k = c_in r + b_in the block entry is
+//   direct (tconj = 0):  Fb[R hi + c_out][lo][a_out][c_in r + b_in]
+//                        (G forward, H adjoint)
+//   tconj = 1:           conj(Fb[R hi + c_in][lo][b_in][c_out r + a_out])
+//                        (H forward, G adjoint)
+template <class T>
+__global__ void k_butterfly(const typename Cx<T>::type *__restrict__ Fb,
+                            const typename Cx<T>::type *__restrict__ x,
+                            typename Cx<T>::type *__restrict__ y, int64_t nb, int64_t blo, int R,
+                            int r, int strided_in, int tconj, int64_t nslots, int64_t npad) {
+  using C = typename Cx<T>::type;
+  const int Rr = R * r;
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= nb * Rr * npad) return;
+  const int64_t n = t % npad;
+  const int o = (int)((t / npad) % Rr);
+  const int64_t b = t / (npad * Rr);
+  const int64_t hi = b / blo, lo = b - hi * blo;
+  const int co = o / r, a = o - co * r;
+  C acc{0, 0};
+  for (int ci = 0; ci < R; ++ci) {
+    const int64_t s_in = slot_of(b, ci, blo, R, strided_in != 0);
+    if (tconj) {
+      const C *blk = Fb + ((R * hi + ci) * blo + lo) * r * Rr;
+      for (int k = 0; k < r; ++k) {
+        const C c = cmulc(x[act_off(s_in, k, n, nslots, r)], blk[k * Rr + co * r + a]);
+        acc.x += c.x;
+        acc.y += c.y;
+      }
+    } else {
+      const C *row = Fb + (((R * hi + co) * blo + lo) * r + a) * Rr + ci * r;
+      for (int k = 0; k < r; ++k) {
+        const C c = cmul(row[k], x[act_off(s_in, k, n, nslots, r)]);
+        acc.x += c.x;
+        acc.y += c.y;
+      }
+    }
+  }
+  const int64_t s_out = slot_of(b, co, blo, R, strided_in == 0);
+  y[act_off(s_out, a, n, nslots, r)] = acc;
+}
+
+// y[(a m + b)][k] = S[a][b][k] x[(b m + a)][k]  (forward, M^h)
+// y[(a m + b)][k] = S[b][a][k] x[(b m + a)][k]  (adjoint, (M^h)^* = (M^h)^T, S real)
+template <class T>
+__global__ void k_middle(const T *__restrict__ S, const typename Cx<T>::type *__restrict__ x,
+                         typename Cx<T>::type *__restrict__ y, int64_t m, int r, int transpose,
+                         int64_t npad) {
+  using C = typename Cx<T>::type;
+  const int64_t nslots = m * m;
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= nslots * r * npad) return;
+  const int64_t n = t % npad;
+  const int k = (int)((t / npad) % r);
+  const int64_t so = t / (npad * r);
+  const int64_t a = so / m, b = so - a * m;
+  const T s = S[(transpose ? b * m + a : so) * r + k];
+  const C v = x[act_off(b * m + a, k, n, nslots, r)];
+  y[act_off(so, k, n, nslots, r)] = C{s * v.x, s * v.y};
+}
+
+// grad[R hi + cx][lo][rx][cy r + ry] = sum_n X[strided(b,cx)][rx][n] conj(Y[contig(b,cy)][ry][n])
+template <class T>
+__global__ void k_level_grad(const typename Cx<T>::type *__restrict__ X,
+                             const typename Cx<T>::type *__restrict__ Y,
+                             typename Cx<T>::type *__restrict__ grad, int64_t nb, int64_t blo,
+                             int R, int r, int64_t nslots, int64_t nrhs) {
+  using C = typename Cx<T>::type;
+  const int Rr = R * r;
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= nb * Rr * Rr) return;
+  const int e2 = (int)(t % Rr);           // cy r + ry
+  const int e1 = (int)((t / Rr) % Rr);    // cx r + rx
+  const int64_t b = t / (Rr * Rr);
+  const int cx = e1 / r, rx = e1 - cx * r;
+  const int cy = e2 / r, ry = e2 - cy * r;
+  const int64_t sx = slot_of(b, cx, blo, R, true);
+  const int64_t sy = slot_of(b, cy, blo, R, false);
+  C acc{0, 0};
+  for (int64_t n = 0; n < nrhs; ++n) {
+    const C c = cmulc(X[act_off(sx, rx, n, nslots, r)], Y[act_off(sy, ry, n, nslots, r)]);
+    acc.x += c.x;
+    acc.y += c.y;
+  }
+  const int64_t hi = b / blo, lo = b - hi * blo;
+  const int64_t p = R * hi + cx;
+  grad[((p * blo + lo) * r + rx) * Rr + e2] = acc;
+}
+
+// grad[j][p][a] = sum_n user[(j n0 + p) ld + n] conj(act[j][a][n])
+template <class T>
+__global__ void k_leaf_grad(const typename Cx<T>::type *__restrict__ user, int64_t ld,
+                            const typename Cx<T>::type *__restrict__ act,
+                            typename Cx<T>::type *__restrict__ grad, int64_t P, int n0, int r,
+                            int64_t nrhs) {
+  using C = typename Cx<T>::type;
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= P * n0 * r) return;
+  const int a = (int)(t % r);
+  const int p = (int)((t / r) % n0);
+  const int64_t j = t / (r * n0);
+  C acc{0, 0};
+  for (int64_t n = 0; n < nrhs; ++n) {
+    const C c = cmulc(user[(j * n0 + p) * ld + n], act[act_off(j, a, n, P, r)]);
+    acc.x += c.x;
+    acc.y += c.y;
+  }
+  grad[t] = acc;
+}
+
+// grad_S[i][j][k] = Re sum_n dz[(i m + j)][k][n] conj(y[(j m + i)][k][n])
+template <class T>
+__global__ void k_middle_grad(const typename Cx<T>::type *__restrict__ dz,
+                              const typename Cx<T>::type *__restrict__ y, T *__restrict__ grad,
+                              int64_t m, int r, int64_t nrhs) {
+  const int64_t nslots = m * m;
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= nslots * r) return;
+  const int k = (int)(t % r);
+  const int64_t s = t / r;
+  const int64_t i = s / m, j = s - i * m;
+  T acc = 0;
+  for (int64_t n = 0; n < nrhs; ++n) {
+    const auto a = dz[act_off(s, k, n, nslots, r)];
+    const auto b = y[act_off(j * m + i, k, n, nslots, r)];
+    acc += a.x * b.x + a.y * b.y;
+  }
+  grad[t] = acc;
+}
+
+inline unsigned blocks_for(int64_t total, int bs) { return (unsigned)((total + bs - 1) / bs); }
+
+template <class T>
+hipError_t level_op_t(const bf_plan *p, const LevelOp &op, const void *in, int64_t ld_in,
+                      void *out, int64_t ld_out, int64_t nrhs, hipStream_t s) {
+  using C = typename Cx<T>::type;
+  const int64_t nchunks = (nrhs + kChunk - 1) / kChunk;
+  const int64_t npad = nchunks * kChunk;
+  const int bs = 256;
+  switch (op.kind) {
+    case LevelOp::kLeafIn:
+      hipLaunchKernelGGL(k_leaf_in<T>, dim3(blocks_for(p->P * p->r * npad, bs)), dim3(bs), 0, s,
+                         (const C *)op.mat, (const C *)in, ld_in, (C *)out, p->P, p->n0, p->r,
+                         nrhs, npad);
+      break;
+    case LevelOp::kButterfly:
+      hipLaunchKernelGGL(k_butterfly<T>, dim3(blocks_for(op.nb * p->R * p->r * npad, bs)),
+                         dim3(bs), 0, s, (const C *)op.mat, (const C *)in, (C *)out, op.nb,
+                         op.blo, p->R, p->r, op.mode == kStridedIn ? 1 : 0, op.tconj ? 1 : 0,
+                         p->P, npad);
+      break;
+    case LevelOp::kMiddle:
+      hipLaunchKernelGGL(k_middle<T>, dim3(blocks_for(p->m * p->m * p->r * npad, bs)), dim3(bs),
+                         0, s, (const T *)op.mat, (const C *)in, (C *)out, p->m, p->r,
+                         op.tconj ? 1 : 0, npad);
+      break;
+    case LevelOp::kLeafOut:
+      hipLaunchKernelGGL(k_leaf_out<T>, dim3(blocks_for(p->P * p->n0 * nrhs, bs)), dim3(bs), 0,
+                         s, (const C *)op.mat, (const C *)in, (C *)out, ld_out, p->P, p->n0,
+                         p->r, nrhs);
+      break;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_level_op(const bf_plan *p, const LevelOp &op, const void *in, int64_t ld_in,
+                           void *out, int64_t ld_out, int64_t nrhs, hipStream_t s) {
+  if (p->prec == BF_PREC_F64) return level_op_t<double>(p, op, in, ld_in, out, ld_out, nrhs, s);
+  return level_op_t<float>(p, op, in, ld_in, out, ld_out, nrhs, s);
+}
+
+hipError_t launch_level_grad(const bf_plan *p, const LevelOp &op, const void *X, const void *Y,
+                             void *grad, int64_t nrhs, hipStream_t s) {
+  const int bs = 256;
+  const int64_t total = op.nb * (int64_t)(p->R * p->r) * (p->R * p->r);
+  if (p->prec == BF_PREC_F64)
+    hipLaunchKernelGGL(k_level_grad<double>, dim3(blocks_for(total, bs)), dim3(bs), 0, s,
+                       (const double2 *)X, (const double2 *)Y, (double2 *)grad, op.nb, op.blo,
+                       p->R, p->r, p->P, nrhs);
+  else
+    hipLaunchKernelGGL(k_level_grad<float>, dim3(blocks_for(total, bs)), dim3(bs), 0, s,
+                       (const float2 *)X, (const float2 *)Y, (float2 *)grad, op.nb, op.blo, p->R,
+                       p->r, p->P, nrhs);
+  return hipGetLastError();
+}
+
+hipError_t launch_leaf_grad(const bf_plan *p, const void *user, int64_t ld, const void *act,
+                            void *grad, int64_t nrhs, hipStream_t s) {
+  const int bs = 256;
+  const int64_t total = p->P * p->n0 * p->r;
+  if (p->prec == BF_PREC_F64)
+    hipLaunchKernelGGL(k_leaf_grad<double>, dim3(blocks_for(total, bs)), dim3(bs), 0, s,
+                       (const double2 *)user, ld, (const double2 *)act, (double2 *)grad, p->P,
+                       p->n0, p->r, nrhs);
+  else
+    hipLaunchKernelGGL(k_leaf_grad<float>, dim3(blocks_for(total, bs)), dim3(bs), 0, s,
+                       (const float2 *)user, ld, (const float2 *)act, (float2 *)grad, p->P,
+                       p->n0, p->r, nrhs);
+  return hipGetLastError();
+}
+
+hipError_t launch_middle_grad(const bf_plan *p, const void *dz, const void *y, void *grad,
+                              int64_t nrhs, hipStream_t s) {
+  const int bs = 256;
+  const int64_t total = p->m * p->m * p->r;
+  if (p->prec == BF_PREC_F64)
+    hipLaunchKernelGGL(k_middle_grad<double>, dim3(blocks_for(total, bs)), dim3(bs), 0, s,
+                       (const double2 *)dz, (const double2 *)y, (double *)grad, p->m, p->r, nrhs);
+  else
+    hipLaunchKernelGGL(k_middle_grad<float>, dim3(blocks_for(total, bs)), dim3(bs), 0, s,
+                       (const float2 *)dz, (const float2 *)y, (float *)grad, p->m, p->r, nrhs);
+  return hipGetLastError();
+}
+
+}  // namespace bfly

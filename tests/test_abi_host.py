@@ -1,0 +1,96 @@
+"""C-ABI checks that need no GPU: the library loads, exports what bf.h declares,
+and rejects bad arguments before touching the device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1502_01379_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    src = open(os.path.join(ROOT, "include", "bf.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(bf_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(B.LIB_PATH):
+        from paper_1502_01379_amd import build
+        build.build()
+    return B.load_library()
+
+
+def test_library_exports_every_declared_symbol(lib):
+    syms = _declared_symbols()
+    assert {"bf_create_from_factors", "bf_apply", "bf_apply_adjoint", "bf_backward",
+            "bf_destroy"} <= set(syms)
+    for s in syms:
+        assert hasattr(lib, s), s
+    assert set(syms) == set(B.EXPORTED)
+
+
+def _factors(shape_tuple):
+    R, leaf, L, r = shape_tuple
+    P = R ** L
+    h = L // 2
+    keep = {"VL": np.zeros(P * leaf * r * 2), "UL": np.zeros(P * leaf * r * 2),
+            "S": np.zeros(R ** h * R ** h * r)}
+    lv = [np.zeros(P * R * r * r * 2) for _ in range(2 * h)]
+    PD = ctypes.POINTER(ctypes.c_double)
+    Harr = (PD * max(h, 1))(*[x.ctypes.data_as(PD) for x in lv[:h]])
+    Garr = (PD * max(h, 1))(*[x.ctypes.data_as(PD) for x in lv[h:]])
+    fh = B.BFFactorsHost(keep["VL"].ctypes.data_as(PD), Harr, keep["S"].ctypes.data_as(PD), Garr,
+                         keep["UL"].ctypes.data_as(PD))
+    return fh, (keep, lv, Harr, Garr)
+
+
+@pytest.mark.parametrize("shape,code", [
+    ((2, 16, 5, 16, 16 * 32), B.BF_ERR_SHAPE),        # odd L
+    ((3, 4, 2, 4, 36), B.BF_ERR_SHAPE),               # radix 3
+    ((2, 16, 4, 16, 1000), B.BF_ERR_SHAPE),           # N != leaf * R^L
+    ((2, 16, 4, 0, 256), B.BF_ERR_SHAPE),             # r = 0
+    ((2, 0, 4, 4, 0), B.BF_ERR_SHAPE),                # leaf 0
+])
+def test_create_rejects_bad_shapes(lib, shape, code):
+    R, leaf, L, r, N = shape
+    fh, keep = _factors((2, 4, 2, 2))
+    st, h = B.bf_create_from_factors(B.BFShape(R, leaf, L, r, N), fh, 1)
+    assert st == code and not h
+    assert B.bf_last_error(None)
+
+
+def test_create_rejects_null_and_nonfinite_and_bad_precision(lib):
+    fh, keep = _factors((2, 4, 2, 2))
+    shape = B.BFShape(2, 4, 2, 2, 16)
+    st, h = B.bf_create_from_factors(shape, B.BFFactorsHost(), 1)
+    assert st == B.BF_ERR_INVALID_ARG and not h
+    st, h = B.bf_create_from_factors(shape, fh, 7)
+    assert st == B.BF_ERR_INVALID_ARG
+    keep[0]["S"][3] = np.nan
+    st, h = B.bf_create_from_factors(shape, fh, 1)
+    assert st == B.BF_ERR_NONFINITE and "NaN" in B.bf_last_error(None)
+    keep[0]["S"][3] = 0
+    keep[1][0][5] = np.inf
+    st, h = B.bf_create_from_factors(shape, fh, 0)
+    assert st == B.BF_ERR_NONFINITE
+
+
+def test_split_precision_needs_fused_shape(lib):
+    # split precision runs only on the fused MFMA passes; radix 4 is not one of them
+    fh, keep = _factors((4, 2, 2, 3))
+    st, h = B.bf_create_from_factors(B.BFShape(4, 2, 2, 3, 32), fh, 2)
+    assert st == B.BF_ERR_UNSUPPORTED and not h
+
+
+def test_null_handle_calls(lib):
+    assert B.bf_apply(None, 1, 2, 1, 1) == B.BF_ERR_INVALID_ARG
+    assert B.bf_apply_adjoint(None, 1, 2, 1, 1) == B.BF_ERR_INVALID_ARG
+    assert B.bf_backward(None, 1, 2, 3, None, 1, 1) == B.BF_ERR_INVALID_ARG
+    B.bf_destroy(None)   # no-op
+    assert lib.bf_set_profiling(None, 1) == B.BF_ERR_INVALID_ARG
