@@ -1,18 +1,408 @@
-// Fused MFMA passes (placeholder until the kernels land).
+// Host side of the fused MFMA passes: the pass plan, the packing of every
+// 32 x 32 complex block into per-lane MFMA operand order, and the launches.
+// Device code: bf_fused_kernel.h.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "bf_fused_kernel.h"
 #include "bf_internal.h"
 
 namespace bfly {
 
-struct FusedPass {};
+using namespace fused;
 
-bool fused_supported(const bf_shape &, bf_precision) { return false; }
-bf_status fused_build(bf_plan *, const bf_factors_host *) { return BF_ERR_UNSUPPORTED; }
-hipError_t fused_run(bf_plan *, bool, const void *, void *, int64_t, int64_t, void *, void *,
-                     hipStream_t) {
-  return hipErrorNotSupported;
+namespace {
+
+using cd = std::complex<double>;
+
+inline int row_of_h(int eta, int rho) { return rho < 4 ? 4 * eta + rho : 8 + 4 * eta + (rho - 4); }
+
+inline uint16_t bf16_rne(float x) {
+  uint32_t u;
+  std::memcpy(&u, &x, 4);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40);  // NaN
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
 }
-void fused_free(FusedPass *fp) { delete fp; }
+inline float bf16_to_f(uint16_t h) {
+  uint32_t u = (uint32_t)h << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+inline uint16_t f16_rne(float x) {
+  _Float16 h = (_Float16)x;  // host conversion, round to nearest even
+  uint16_t u;
+  std::memcpy(&u, &h, 2);
+  return u;
+}
+inline float f16_to_f(uint16_t u) {
+  _Float16 h;
+  std::memcpy(&h, &u, 2);
+  return (float)h;
+}
+
+// Lay out one 32 x 32 complex block M[o][k] (o = c r + a, k = c' r + b) as the
+// per-lane A operands of block_f32 / block_split.  Returns the FP16 block scale.
+float pack_block(const cd *M, int prec, char *dst) {
+  if (prec == kF32) {
+    float *o = reinterpret_cast<float *>(dst);
+    for (int lane = 0; lane < 64; ++lane) {
+      const int i = lane & 31, eta = lane >> 5;
+      for (int s = 0; s < 32; ++s) {
+        const int part = s >> 4, cp = (s >> 3) & 1, rho = s & 7;
+        const cd v = M[i * 32 + cp * 16 + row_of_h(eta, rho)];
+        o[((s >> 2) * 64 + lane) * 4 + (s & 3)] = (float)(part == 0 ? v.real() : -v.imag());
+      }
+    }
+    return 1.f;
+  }
+  double mx = 0;
+  for (int e = 0; e < 1024; ++e) mx = std::max(mx, std::max(std::fabs(M[e].real()), std::fabs(M[e].imag())));
+  float bscale = 1.f;
+  double pre = 1.0;
+  if (prec == kF16 && mx > 0) {
+    int ex = 0;
+    std::frexp(mx, &ex);
+    pre = std::ldexp(1.0, -ex);           // block entries scaled into [0.5, 1)
+    bscale = (float)std::ldexp(1.0, ex);  // undone on the accumulator
+  }
+  uint16_t *o = reinterpret_cast<uint16_t *>(dst);
+  for (int lane = 0; lane < 64; ++lane) {
+    const int i = lane & 31, eta = lane >> 5;
+    for (int t = 0; t < 4; ++t) {
+      const int part = t >> 1, cp = t & 1;
+      for (int j = 0; j < 8; ++j) {
+        const cd v = M[i * 32 + cp * 16 + row_of_h(eta, j)];
+        const float x = (float)((part == 0 ? v.real() : -v.imag()) * pre);
+        uint16_t h, l;
+        if (prec == kBF16) {
+          h = bf16_rne(x);
+          l = bf16_rne(x - bf16_to_f(h));
+        } else {
+          h = f16_rne(x);
+          l = f16_rne(x - f16_to_f(h));
+        }
+        o[((t * 64) + lane) * 8 + j] = h;
+        o[(((4 + t) * 64) + lane) * 8 + j] = l;
+      }
+    }
+  }
+  return bscale;
+}
+
+}  // namespace
+
+struct FusedPass {
+  int K = 0, log_slo = 0, mode_si = 1, in_kind = kInAct, out_kind = kOutAct;
+  int64_t ntiles = 0;
+  void *fac = nullptr, *leaf = nullptr;
+  float *fscale = nullptr, *lscale = nullptr;
+  const float *Sm = nullptr;
+  std::string name;
+  std::vector<void *> owned;
+};
+
+namespace {
+
+struct HostFactors {
+  const bf_factors_host *f;
+  int L, h;
+  // canonical accessors (complex, FP64)
+  cd H(int l, int64_t p, int64_t q, int row, int col) const {
+    const int64_t blo = int64_t(1) << (L - l - 1);
+    const double *b = f->H[l - h] + (((p * blo + q) * kRank + row) * 2 * kRank + col) * 2;
+    return cd(b[0], b[1]);
+  }
+  cd G(int l, int64_t p, int64_t q, int row, int col) const {
+    const int64_t blo = int64_t(1) << (L - l - 1);
+    const double *b = f->G[l - h] + (((p * blo + q) * kRank + row) * 2 * kRank + col) * 2;
+    return cd(b[0], b[1]);
+  }
+  cd leafV(int64_t j, int p, int a) const {
+    const double *b = f->VL + ((j * kRank + p) * kRank + a) * 2;
+    return cd(b[0], b[1]);
+  }
+  cd leafU(int64_t j, int p, int a) const {
+    const double *b = f->UL + ((j * kRank + p) * kRank + a) * 2;
+    return cd(b[0], b[1]);
+  }
+};
+
+// Which factor a pass applies.
+enum PassSide : int { kHfwd, kGfwd, kGadj, kHadj };
+
+struct PassPlan {
+  PassSide side;
+  int K, l_hi, l_lo;
+  int in_kind, out_kind;
+};
+
+// Block of depth d, local butterfly (ap, b) of tile (hi, lo), as M[o][k].
+void butterfly_block(const HostFactors &F, const PassPlan &pp, int d, int64_t hi, int64_t lo,
+                     int ap, int b, cd *M) {
+  const int K = pp.K;
+  const int r = kRank;
+  if (pp.side == kHfwd) {  // M[c r + a][c' r + b'] = conj(H_l[2j + c'][i][b'][c r + a])
+    const int l = pp.l_hi - d - 1;
+    const int64_t j = (hi << (K - d - 1)) + ap, i = (lo << d) + b;
+    for (int c = 0; c < 2; ++c)
+      for (int a = 0; a < r; ++a)
+        for (int cp = 0; cp < 2; ++cp)
+          for (int bb = 0; bb < r; ++bb)
+            M[(c * r + a) * 32 + cp * r + bb] = std::conj(F.H(l, 2 * j + cp, i, bb, c * r + a));
+  } else if (pp.side == kGfwd) {  // M[c r + a][c' r + b'] = G_l[2i + c][j][a][c' r + b']
+    const int l = pp.l_lo + d;
+    const int64_t i = (hi << d) + b, j = (lo << (K - d - 1)) + ap;
+    for (int c = 0; c < 2; ++c)
+      for (int a = 0; a < r; ++a)
+        for (int k = 0; k < 2 * r; ++k) M[(c * r + a) * 32 + k] = F.G(l, 2 * i + c, j, a, k);
+  } else if (pp.side == kGadj) {  // M[co r + b'][ci r + a] = conj(G_l[2i + ci][j][a][co r + b'])
+    const int l = pp.l_hi - d - 1;
+    const int64_t i = (hi << (K - d - 1)) + ap, j = (lo << d) + b;
+    for (int co = 0; co < 2; ++co)
+      for (int bb = 0; bb < r; ++bb)
+        for (int ci = 0; ci < 2; ++ci)
+          for (int a = 0; a < r; ++a)
+            M[(co * r + bb) * 32 + ci * r + a] = std::conj(F.G(l, 2 * i + ci, j, a, co * r + bb));
+  } else {  // kHadj: M[co r + b'][ci r + a] = H_l[2j + co][i][b'][ci r + a]
+    const int l = pp.l_lo + d;
+    const int64_t j = (hi << d) + b, i = (lo << (K - d - 1)) + ap;
+    for (int co = 0; co < 2; ++co)
+      for (int bb = 0; bb < r; ++bb)
+        for (int k = 0; k < 2 * r; ++k) M[(co * r + bb) * 32 + k] = F.H(l, 2 * j + co, i, bb, k);
+  }
+}
+
+// Leaf pair (leaves j0, j0 + 1) as a block-diagonal 32 x 32 block.
+//   in  (conj-transposed):  M[c r + a][c r + p] = conj(W[j0 + c][p][a])
+//   out:                    M[c r + p][c r + a] = W[j0 + c][p][a]
+void leaf_block(const HostFactors &F, bool use_v, bool in, int64_t j0, cd *M) {
+  std::fill(M, M + 1024, cd(0, 0));
+  for (int c = 0; c < 2; ++c)
+    for (int p = 0; p < kRank; ++p)
+      for (int a = 0; a < kRank; ++a) {
+        const cd w = use_v ? F.leafV(j0 + c, p, a) : F.leafU(j0 + c, p, a);
+        if (in)
+          M[(c * kRank + a) * 32 + c * kRank + p] = std::conj(w);
+        else
+          M[(c * kRank + p) * 32 + c * kRank + a] = w;
+      }
+}
+
+template <class Fn>
+void parallel_for(int64_t n, Fn fn) {
+  const unsigned nt = std::max(1u, std::min(32u, std::thread::hardware_concurrency()));
+  if (n < 64 || nt == 1) {
+    for (int64_t i = 0; i < n; ++i) fn(i);
+    return;
+  }
+  std::vector<std::thread> th;
+  for (unsigned t = 0; t < nt; ++t)
+    th.emplace_back([&, t] {
+      for (int64_t i = (int64_t)(n * t / nt); i < (int64_t)(n * (t + 1) / nt); ++i) fn(i);
+    });
+  for (auto &x : th) x.join();
+}
+
+std::vector<int> split_levels(int h, int kmax) {
+  const int np = (h + kmax - 1) / kmax;
+  std::vector<int> ks;
+  for (int i = 0; i < np; ++i) ks.push_back(h / np + (i < h % np ? 1 : 0));
+  return ks;
+}
+
+bf_status upload(bf_plan *p, FusedPass *fp, const void *src, size_t bytes, void **dst) {
+  void *d = nullptr;
+  hipError_t e = hipMalloc(&d, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    p->err = std::string("fused pack allocation: ") + hipGetErrorString(e);
+    return BF_ERR_ALLOC;
+  }
+  fp->owned.push_back(d);
+  e = hipMemcpy(d, src, bytes, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    p->err = std::string("fused pack upload: ") + hipGetErrorString(e);
+    return BF_ERR_HIP;
+  }
+  *dst = d;
+  return BF_OK;
+}
+
+bf_status build_pass(bf_plan *p, const HostFactors &F, const PassPlan &pp, int prec,
+                     const float *Sm, FusedPass **out) {
+  FusedPass *fp = new FusedPass();
+  *out = fp;
+  const int K = pp.K, L = p->L;
+  const int NB = 1 << (K - 1);
+  fp->K = K;
+  fp->log_slo = L - pp.l_hi;
+  fp->mode_si = (pp.side == kHfwd || pp.side == kGadj) ? 1 : 0;
+  fp->in_kind = pp.in_kind;
+  fp->out_kind = pp.out_kind;
+  fp->ntiles = int64_t(1) << (L - K);
+  fp->Sm = Sm;
+  static const char *side_name[] = {"H_fwd", "G_fwd", "G_adj", "H_adj"};
+  fp->name = std::string("fused_") + side_name[pp.side] + "_l" + std::to_string(pp.l_hi) + "_" +
+             std::to_string(pp.l_lo);
+  const int64_t ntiles = fp->ntiles;
+  const int64_t nblk = (int64_t)K * ntiles * NB;
+  std::vector<char> buf((size_t)nblk * kBlockBytes);
+  std::vector<float> sc((size_t)nblk, 1.f);
+  parallel_for(ntiles, [&](int64_t tile) {
+    std::vector<cd> M(1024);
+    const int64_t hi = tile >> fp->log_slo, lo = tile & ((int64_t(1) << fp->log_slo) - 1);
+    for (int d = 0; d < K; ++d)
+      for (int ap = 0; ap < (1 << (K - d - 1)); ++ap)
+        for (int b = 0; b < (1 << d); ++b) {
+          const int beta = ap * (1 << d) + b;
+          const int64_t bi = ((int64_t)d * ntiles + tile) * NB + beta;
+          butterfly_block(F, pp, d, hi, lo, ap, b, M.data());
+          sc[bi] = pack_block(M.data(), prec, buf.data() + bi * kBlockBytes);
+        }
+  });
+  bf_status st = upload(p, fp, buf.data(), buf.size(), &fp->fac);
+  if (st == BF_OK && prec == kF16)
+    st = upload(p, fp, sc.data(), sc.size() * sizeof(float), (void **)&fp->fscale);
+  if (st != BF_OK) return st;
+  if (pp.in_kind == kInUser || pp.out_kind == kOutUser) {
+    // first pass of a direction: leaf in (V^* forward, U^* adjoint);
+    // last pass: leaf out (U forward, V adjoint)
+    const bool in = pp.in_kind == kInUser;
+    const bool use_v = in ? (pp.side == kHfwd) : (pp.side == kHadj);
+    std::vector<char> lb((size_t)ntiles * NB * kBlockBytes);
+    std::vector<float> ls((size_t)ntiles * NB, 1.f);
+    parallel_for(ntiles, [&](int64_t tile) {
+      std::vector<cd> M(1024);
+      for (int q = 0; q < NB; ++q) {
+        const int64_t bi = tile * NB + q;
+        leaf_block(F, use_v, in, (tile << K) + 2 * q, M.data());
+        ls[bi] = pack_block(M.data(), prec, lb.data() + bi * kBlockBytes);
+      }
+    });
+    st = upload(p, fp, lb.data(), lb.size(), &fp->leaf);
+    if (st == BF_OK && prec == kF16)
+      st = upload(p, fp, ls.data(), ls.size() * sizeof(float), (void **)&fp->lscale);
+  }
+  return st;
+}
+
+hipError_t launch_pass(const bf_plan *p, const FusedPass *fp, const void *in, void *out,
+                       int64_t nrhs, int64_t ld, hipStream_t s) {
+  FusedArgs a;
+  a.in = in;
+  a.out = out;
+  a.fac = static_cast<const char *>(fp->fac);
+  a.leaf = static_cast<const char *>(fp->leaf);
+  a.fscale = fp->fscale;
+  a.lscale = fp->lscale;
+  a.Sm = fp->Sm;
+  a.ld = ld;
+  a.nrhs = nrhs;
+  a.nchunks = (nrhs + kChunk - 1) / kChunk;
+  a.nslots = p->P;
+  a.ntiles = fp->ntiles;
+  a.m = p->m;
+  a.log_slo = fp->log_slo;
+  a.mode_si = fp->mode_si;
+  a.in_kind = fp->in_kind;
+  a.out_kind = fp->out_kind;
+  const dim3 grid((unsigned)fp->ntiles, (unsigned)((a.nchunks + kWaves - 1) / kWaves));
+  const bool li = fp->in_kind == kInUser, lo = fp->out_kind == kOutUser;
+  if (p->prec == BF_PREC_F32) return launch_prec<kF32>(a, fp->K, li, lo, grid, s);
+  if (p->prec == BF_PREC_SPLIT_BF16) return launch_prec<kBF16>(a, fp->K, li, lo, grid, s);
+  return launch_prec<kF16>(a, fp->K, li, lo, grid, s);
+}
+
+}  // namespace
+
+bool fused_supported(const bf_shape &sh, bf_precision prec) {
+  if (std::getenv("BF_DISABLE_FUSED")) return false;
+  return prec != BF_PREC_F64 && sh.radix == 2 && sh.leaf == kRank && sh.r == kRank && sh.L >= 2;
+}
+
+bf_status fused_build(bf_plan *p, const bf_factors_host *f) {
+  HostFactors F{f, p->L, p->h};
+  int kmax = kDefaultK;
+  if (const char *e = std::getenv("BF_FUSED_KMAX")) kmax = std::max(1, std::min(kMaxK, std::atoi(e)));
+  const int prec = p->prec == BF_PREC_F32 ? kF32 : p->prec == BF_PREC_SPLIT_BF16 ? kBF16 : kF16;
+
+  // middle weights as FP32 in natural slot order: S for the forward, S^T for the adjoint
+  const int64_t m = p->m;
+  std::vector<float> S((size_t)m * m * kRank), ST((size_t)m * m * kRank);
+  for (int64_t i = 0; i < m; ++i)
+    for (int64_t j = 0; j < m; ++j)
+      for (int k = 0; k < kRank; ++k) {
+        const float v = (float)f->S[(i * m + j) * kRank + k];
+        S[(i * m + j) * kRank + k] = v;
+        ST[(j * m + i) * kRank + k] = v;
+      }
+  FusedPass holder;
+  void *dS = nullptr, *dST = nullptr;
+  bf_status st = upload(p, &holder, S.data(), S.size() * 4, &dS);
+  if (st == BF_OK) st = upload(p, &holder, ST.data(), ST.size() * 4, &dST);
+  for (void *d : holder.owned) p->allocs.push_back(d);
+  if (st != BF_OK) return st;
+
+  const std::vector<int> ks = split_levels(p->h, kmax);
+  for (int dir = 0; dir < 2; ++dir) {
+    const bool adj = dir == 1;
+    auto &list = adj ? p->adj_passes : p->fwd_passes;
+    // first side: from the leaves (level L) down to the middle (level h)
+    int l_hi = p->L;
+    for (size_t t = 0; t < ks.size(); ++t) {
+      PassPlan pp{adj ? kGadj : kHfwd, ks[t], l_hi, l_hi - ks[t], t == 0 ? kInUser : kInAct, kOutAct};
+      FusedPass *fp = nullptr;
+      st = build_pass(p, F, pp, prec, nullptr, &fp);
+      list.push_back(fp);
+      if (st != BF_OK) return st;
+      l_hi -= ks[t];
+    }
+    // second side: from the middle (level h) up to the leaves
+    int l_lo = p->h;
+    for (size_t t = 0; t < ks.size(); ++t) {
+      const int K = ks[ks.size() - 1 - t];
+      PassPlan pp{adj ? kHadj : kGfwd, K, l_lo + K, l_lo, t == 0 ? kInMiddle : kInAct,
+                  t + 1 == ks.size() ? kOutUser : kOutAct};
+      FusedPass *fp = nullptr;
+      st = build_pass(p, F, pp, prec, t == 0 ? (const float *)(adj ? dST : dS) : nullptr, &fp);
+      list.push_back(fp);
+      if (st != BF_OK) return st;
+      l_lo += K;
+    }
+  }
+  return BF_OK;
+}
+
+hipError_t fused_run(bf_plan *p, bool adjoint, const void *g, void *u, int64_t nrhs, int64_t ld,
+                     void *buf0, void *buf1, hipStream_t s) {
+  const auto &list = adjoint ? p->adj_passes : p->fwd_passes;
+  const void *cur = g;
+  void *bufs[2] = {buf0, buf1};
+  for (size_t t = 0; t < list.size(); ++t) {
+    void *dst = (t + 1 == list.size()) ? u : bufs[t & 1];
+    prof_begin(p, list[t]->name, s);
+    hipError_t e = launch_pass(p, list[t], cur, dst, nrhs, ld, s);
+    prof_end(p, s);
+    if (e != hipSuccess) return e;
+    cur = dst;
+  }
+  return hipSuccess;
+}
+
+void fused_free(FusedPass *fp) {
+  if (!fp) return;
+  for (void *d : fp->owned) (void)hipFree(d);
+  delete fp;
+}
 
 }  // namespace bfly

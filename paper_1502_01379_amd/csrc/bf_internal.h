@@ -12,15 +12,17 @@
 namespace bfly {
 
 // Activation layout used by every kernel between launches: right-hand sides are
-// grouped in chunks of 32 (one chunk per wavefront of the fused kernels), and a
-// chunk holds, for every slot, r rows of 32 interleaved complex values:
-//   element (slot, row, n) -> ((n / 32) * nslots + slot) * r * 32 + row * 32 + n % 32
+// grouped in chunks of 32 (one chunk per wavefront of the fused kernels); a
+// chunk holds, for every slot, its r rows in pairs, each pair stored as 32
+// columns of two interleaved complex values (16 bytes per column in FP32):
+//   element (slot, row, n) -> ((n / 32 * nslots + slot) * ceil(r/2) + row / 2) * 64
+//                             + (n % 32) * 2 + row % 2
 // nslots = R^L at every level of the tree (R^l nodes of one tree times R^(L-l)
 // nodes of the other).
 constexpr int kChunk = 32;
 
 inline int64_t act_elems(int64_t nslots, int r, int64_t nchunks) {
-  return nchunks * nslots * r * kChunk;
+  return nchunks * nslots * ((r + 1) / 2) * 2 * kChunk;
 }
 
 // Slot patterns of one butterfly level.  Butterfly b = hi * blo + lo combines R

@@ -35,8 +35,10 @@ template <class C> __device__ __forceinline__ C cmulc(C a, C b) {
   return o;
 }
 
+// Row-pair layout shared with the fused passes (see bf_internal.h).
 __device__ __forceinline__ int64_t act_off(int64_t slot, int row, int64_t n, int64_t nslots, int r) {
-  return (((n >> 5) * nslots + slot) * r + row) * kChunk + (n & 31);
+  const int rp = (r + 1) >> 1;
+  return (((n >> 5) * nslots + slot) * rp + (row >> 1)) * (2 * kChunk) + (n & 31) * 2 + (row & 1);
 }
 
 __device__ __forceinline__ int64_t slot_of(int64_t b, int c, int64_t blo, int R, bool strided) {

@@ -1,0 +1,138 @@
+"""Fused MFMA passes (binary trees, 16-point leaves, rank 16) vs the FP64 oracle.
+
+FP32 is held to 1e-5 and split BF16 to 1e-4 relative l2 error (the stated
+budgets); split FP16 to 1e-5.  Parity is on identical factors.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from bf_inputs import complex_gaussian, synthetic_factors
+from oracle import kernels
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = {"f32": 1e-5, "bf16x3": 1e-4, "f16x3": 1e-5}
+PRECS = ["f32", "bf16x3", "f16x3"]
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1502_01379_amd import load_library
+    load_library()
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def fio4096():
+    return oracle.construct_factors(kernels.fio(4096), leaf=16, r=16, method="sampling", seed=0)
+
+
+def _handle(f, prec, kmax=None):
+    from paper_1502_01379_amd import BFHandle
+    old = os.environ.get("BF_FUSED_KMAX")
+    if kmax is not None:
+        os.environ["BF_FUSED_KMAX"] = str(kmax)
+    try:
+        h = BFHandle(f, prec)
+    finally:
+        if kmax is not None:
+            if old is None:
+                del os.environ["BF_FUSED_KMAX"]
+            else:
+                os.environ["BF_FUSED_KMAX"] = old
+    assert h.path == 1, "expected the fused MFMA path"
+    return h
+
+
+def _dev(x, dev):
+    return torch.as_tensor(x).to(dev, torch.complex64)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("nrhs,pad", [(64, 0), (1, 0), (33, 3), (130, 2)])
+def test_fused_apply_and_adjoint(dev, fio4096, prec, nrhs, pad):
+    f = fio4096
+    N = 4096
+    g = complex_gaussian((N, nrhs), 100 + nrhs)
+    gl = np.zeros((N, nrhs + pad), dtype=complex)
+    gl[:, :nrhs] = g
+    gd = _dev(gl, dev)[:, :nrhs]
+    h = _handle(f, prec)
+    u = h.apply(gd).cpu().numpy()
+    assert oracle.rel_err(u, oracle.bf_apply(f, g)) < TOL[prec]
+    v = h.apply_adjoint(gd).cpu().numpy()
+    assert oracle.rel_err(v, oracle.bf_apply_adjoint(f, g)) < TOL[prec]
+
+
+@pytest.mark.parametrize("kmax", [1, 2, 3])
+def test_fused_pass_depths_agree(dev, fio4096, kmax):
+    # the same factor product split into passes of 1, 2 or 3 levels
+    g = complex_gaussian((4096, 40), 5)
+    ref = oracle.bf_apply(fio4096, g)
+    h = _handle(fio4096, "f32", kmax=kmax)
+    u = h.apply(_dev(g, dev)).cpu().numpy()
+    assert oracle.rel_err(u, ref) < TOL["f32"]
+
+
+@pytest.mark.parametrize("L", [2, 4, 6, 10])
+def test_fused_tree_depths(dev, L):
+    # every even depth: one pass per side (L <= 6) or several
+    f = synthetic_factors(2, 16, L, 16, seed=L)
+    N = 16 * 2 ** L
+    g = complex_gaussian((N, 35), L)
+    for prec in PRECS:
+        h = _handle(f, prec)
+        u = h.apply(_dev(g, dev)).cpu().numpy()
+        assert oracle.rel_err(u, oracle.bf_apply(f, g)) < TOL[prec], prec
+        v = h.apply_adjoint(_dev(g, dev)).cpu().numpy()
+        assert oracle.rel_err(v, oracle.bf_apply_adjoint(f, g)) < TOL[prec], prec
+
+
+def test_unit_vectors_layout_fused(dev):
+    # unit vectors: every column of K_BF lands where the oracle puts it
+    f = synthetic_factors(2, 16, 4, 16, seed=3)
+    N = 256
+    eye = np.eye(N, dtype=complex)
+    h = _handle(f, "f32")
+    cols = h.apply(_dev(eye, dev)).cpu().numpy()
+    ref = oracle.bf_apply(f, eye)
+    assert np.abs(cols - ref).max() <= 1e-5 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "f32"])
+def test_backward_on_fused_handle(dev, fio4096, prec):
+    f = fio4096
+    g = complex_gaussian((4096, 24), 7)
+    gu = complex_gaussian((4096, 24), 8)
+    ref = oracle.bf_grad(f, g, gu)
+    h = _handle(f, prec)
+    grad_g, grads = h.backward(_dev(g, dev), _dev(gu, dev))
+    assert oracle.rel_err(grad_g.cpu().numpy(), ref["g"]) < 1e-5
+    assert oracle.rel_err(grads["H"][0].cpu().numpy(), ref["H"][0]) < 1e-4
+    assert oracle.rel_err(grads["S"].cpu().numpy(), ref["S"]) < 1e-4
+
+
+def test_full_size_2_20_256_rhs(dev):
+    # N = 2^20, leaf 16, r = 16 (L = 16), 256 right-hand sides; synthetic factors of
+    # the real shapes; every row of three sampled columns is compared with the oracle
+    f = synthetic_factors(2, 16, 16, 16, seed=20)
+    N = 1 << 20
+    g = complex_gaussian((N, 256), 21, dtype=np.complex64)
+    gd = torch.from_numpy(g).to(dev)
+    cols = [0, 131, 255]
+    ref = oracle.bf_apply(f, g[:, cols].astype(np.complex128))
+    for prec in ["f32", "bf16x3"]:
+        h = _handle(f, prec)
+        u = h.apply(gd)
+        torch.cuda.synchronize()
+        err = oracle.rel_err(u[:, cols].cpu().numpy(), ref)
+        print(f"N=2^20 {prec} rel err {err:.3e}", flush=True)
+        assert err < TOL[prec]
+        h.close()
+        del u
