@@ -1,0 +1,220 @@
+"""Benchmark of the butterfly-factorization apply on one MI355X.
+
+Workload: the 1D Fourier integral operator shape at N = 2^20 (leaf 16, so
+L = 16 binary levels), rank r = 16, 256 right-hand sides of iid complex
+Gaussian g.  The factors are seeded synthetic blocks of exactly the shapes a
+factorization of that operator has (building one on a CPU takes hours); the
+apply's cost does not depend on their values.  Inputs are resident in HBM
+before timing starts.
+
+One step = one bf_apply over the whole batch (all passes: leaf projection,
+H levels, middle weights, G levels, leaf expansion).  Prints one JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--precision bf16x3|f32|f16x3]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "BF apply RHS·N/s at stated rel. err (FP32 vs split-BF16 vs FP64); % roofline"
+HBM_PEAK_GBS = 8000.0
+PEAK_TFLOPS = {"f32": 157.3, "bf16x3": 2516.6, "f16x3": 2516.6}   # dense MFMA, per dtype
+MFMA_WORK = {"f32": 1.0, "bf16x3": 3.0, "f16x3": 3.0}              # MFMA products per algorithmic one
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--precision", default="bf16x3", choices=["bf16x3", "f32", "f16x3"])
+    ap.add_argument("--variants", default="f32", help="comma list of extra precisions to time")
+    ap.add_argument("--log2n", type=int, default=20)
+    ap.add_argument("--nrhs", type=int, default=256)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a 1 GiB device copy (reference for HBM byte counters)")
+    return ap.parse_args()
+
+
+def pass_work(name, L, r, leaf, nrhs, K, has_leaf, has_middle):
+    """Algorithmic flops and compulsory HBM bytes of one fused-pass launch.
+
+    Unit: one butterfly (a 2r x 2r complex block) applied to one right-hand
+    side = (2r)^2 complex multiply-adds = 8 (2r)^2 real flops.  A pass of K
+    levels applies K 2^(L-1) of them per column, plus N r multiply-adds per
+    column for a leaf block.  Its compulsory traffic is its input and output
+    activations (P r complex64 per column each), its factor blocks (K 2^(L-1)
+    blocks of (2r)^2 complex64), the leaf blocks (N r complex64) and the
+    middle weights (P r float32).
+    """
+    P = 2 ** L
+    N = P * leaf
+    cm = K * (P // 2) * (2 * r) ** 2 + (N * r if has_leaf else 0)
+    flops = 8.0 * cm * nrhs
+    act = P * r * 8.0 * nrhs
+    fac = K * (P // 2) * (2 * r) ** 2 * 8.0 + (N * r * 8.0 if has_leaf else 0.0)
+    mid = P * r * 4.0 if has_middle else 0.0
+    return flops, 2 * act + fac + mid
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the library has no "
+              "multi-GPU path. Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from bf_inputs import complex_gaussian, synthetic_factors
+    from paper_1502_01379_amd import BFHandle
+
+    dev = torch.device("cuda:0")
+    L = args.log2n - 4
+    leaf, r, nrhs = 16, 16, args.nrhs
+    N = leaf * 2 ** L
+    t0 = time.time()
+    f = synthetic_factors(2, leaf, L, r, seed=20)
+    g_host = complex_gaussian((N, nrhs), 21, dtype=np.complex64)
+    g = torch.from_numpy(g_host).to(dev)
+    u = torch.empty_like(g)
+    print(f"[bench] inputs ready in {time.time() - t0:.1f}s (N={N}, nrhs={nrhs})", file=sys.stderr, flush=True)
+
+    precisions = [args.precision] + [p for p in args.variants.split(",") if p and p != args.precision]
+    results = {}
+    for prec in precisions:
+        t1 = time.time()
+        h = BFHandle(f, prec)
+        print(f"[bench] {prec}: handle created in {time.time() - t1:.1f}s (path {h.path})",
+              file=sys.stderr, flush=True)
+        stream = torch.cuda.current_stream()
+        for _ in range(args.warmup):
+            h.apply(g, out=u)
+        torch.cuda.synchronize()
+        h.set_profiling(True)
+        h.kernel_times(reset=True)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        for _ in range(args.steps):
+            h.apply(g, out=u)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / args.steps
+        kt = h.kernel_times(reset=True)
+        h.set_profiling(False)
+        results[prec] = {"ms": ms, "kernels": kt, "handle": h, "u_cols": None}
+        print(f"[bench] {prec}: {ms:.3f} ms/step", file=sys.stderr, flush=True)
+        cols = [0, nrhs // 2, nrhs - 1]
+        results[prec]["u_cols"] = u[:, cols].cpu().numpy()
+        h.close()
+
+    # oracle: FP64 apply of the same factors on a bounded sample of columns, on one core
+    cpu = None
+    cols = [0, nrhs // 2, nrhs - 1]
+    ref = None
+    if not args.no_cpu_baseline:
+        import oracle
+        try:
+            from threadpoolctl import threadpool_limits
+            limiter = threadpool_limits(1)
+        except Exception:
+            limiter = None
+        ncol = 2
+        t2 = time.time()
+        sub = oracle.bf_apply(f, g_host[:, cols[:ncol]].astype(np.complex128))
+        dt = time.time() - t2
+        if limiter is not None:
+            limiter.unregister()
+        ref = oracle.bf_apply(f, g_host[:, cols[ncol:]].astype(np.complex128))
+        ref = np.concatenate([sub, ref], axis=1)
+        cpu = {"value": ncol * N / dt, "unit": "RHS·N/s", "cores": 1, "kind": "oracle",
+               "sample": f"FP64 oracle apply of the same factors to {ncol} of the {nrhs} columns "
+                         f"(N={N}), {dt:.1f}s, one thread"}
+
+    # roofline of the dominant kernel of the headline precision
+    main_res = results[args.precision]
+    kt = main_res["kernels"]
+    name, (tot_ms, launches) = max(kt.items(), key=lambda kv: kv[1][0])
+    avg_ms = tot_ms / max(1, launches)
+    # parse the pass name fused_<side>_l<hi>_<lo>
+    parts = name.split("_")            # fused_<H|G>_<fwd|adj>_l<hi>_<lo>
+    l_hi, l_lo = int(parts[3][1:]), int(parts[4])
+    K = l_hi - l_lo
+    has_leaf = (l_hi == L and parts[1] in ("H", "G"))
+    has_middle = (l_lo == L // 2 and parts[1] == "G")
+    flops, bytes_ = pass_work(name, L, r, leaf, nrhs, K, has_leaf, has_middle)
+    mfma_flops = flops * MFMA_WORK[args.precision]
+    t_mfma = mfma_flops / (PEAK_TFLOPS[args.precision] * 1e12)
+    t_hbm = bytes_ / (HBM_PEAK_GBS * 1e9)
+    if t_mfma >= t_hbm:
+        roof = {"bound": "mfma", "achieved": mfma_flops / (avg_ms * 1e-3) / 1e12,
+                "peak": PEAK_TFLOPS[args.precision], "unit": "TFLOP/s"}
+    else:
+        roof = {"bound": "hbm", "achieved": bytes_ / (avg_ms * 1e-3) / 1e9,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["kernel"] = name
+    roof["avg_launch_ms"] = avg_ms
+    roof["launches"] = launches
+
+    def rel(u_cols):
+        if ref is None:
+            return None
+        d = u_cols.astype(np.complex128) - ref
+        return float(np.sqrt(np.sum(np.abs(d) ** 2) / np.sum(np.abs(ref) ** 2)))
+
+    variants = {}
+    for prec, res in results.items():
+        variants[prec] = {"value": nrhs * N / (res["ms"] * 1e-3), "ms_per_step": res["ms"],
+                          "rel_err_vs_fp64": rel(res["u_cols"]),
+                          "kernels_ms_per_launch": {k: v[0] / max(1, v[1]) for k, v in res["kernels"].items()}}
+
+    if args.copy_probe:
+        x = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+
+    ms = main_res["ms"]
+    out = {
+        "metric": METRIC,
+        "value": nrhs * N / (ms * 1e-3),
+        "unit": "RHS·N/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"bf16x3": "bf16", "f16x3": "f16", "f32": "f32"}[args.precision],
+        "precision": {"bf16x3": "split BF16: hi*hi + hi*lo + lo*hi MFMA products, FP32 accumulation",
+                      "f16x3": "split FP16: three MFMA products, FP32 accumulation, power-of-two scaling",
+                      "f32": "FP32 MFMA"}[args.precision],
+        "rel_err_vs_fp64": variants[args.precision]["rel_err_vs_fp64"],
+        "data": "synthetic",
+        "config": {"workload": f"1D FIO-shaped butterfly factorization, N=2^{args.log2n}, leaf 16 "
+                               f"(L={L}), r=16, {nrhs} RHS, seeded synthetic factor blocks",
+                   "N": N, "leaf": leaf, "L": L, "r": r, "nrhs": nrhs},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "variants": variants,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

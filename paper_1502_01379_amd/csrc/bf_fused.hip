@@ -316,11 +316,10 @@ hipError_t launch_pass(const bf_plan *p, const FusedPass *fp, const void *in, vo
   a.mode_si = fp->mode_si;
   a.in_kind = fp->in_kind;
   a.out_kind = fp->out_kind;
-  const dim3 grid((unsigned)fp->ntiles, (unsigned)((a.nchunks + kWaves - 1) / kWaves));
   const bool li = fp->in_kind == kInUser, lo = fp->out_kind == kOutUser;
-  if (p->prec == BF_PREC_F32) return launch_prec<kF32>(a, fp->K, li, lo, grid, s);
-  if (p->prec == BF_PREC_SPLIT_BF16) return launch_prec<kBF16>(a, fp->K, li, lo, grid, s);
-  return launch_prec<kF16>(a, fp->K, li, lo, grid, s);
+  if (p->prec == BF_PREC_F32) return launch_prec<kF32>(a, fp->K, li, lo, s);
+  if (p->prec == BF_PREC_SPLIT_BF16) return launch_prec<kBF16>(a, fp->K, li, lo, s);
+  return launch_prec<kF16>(a, fp->K, li, lo, s);
 }
 
 }  // namespace

@@ -56,7 +56,7 @@ constexpr int kRank = 16;          // r == n0 == 16
 constexpr int kBlockBytes = 8192;  // packed A operands of one 32 x 32 complex block
 constexpr int kMaxK = 4;          // deepest compiled pass
 constexpr int kDefaultK = 3;      // deepest pass used unless BF_FUSED_KMAX says otherwise
-constexpr int kWaves = 4;          // wavefronts per workgroup
+constexpr int kWaves = 8;          // most wavefronts (right-hand-side chunks) per workgroup
 
 enum InKind : int { kInAct = 0, kInUser = 1, kInMiddle = 2 };
 enum OutKind : int { kOutAct = 0, kOutUser = 1 };
@@ -238,15 +238,28 @@ __device__ __forceinline__ int64_t op_block(const FusedArgs &a, int64_t tile, in
   return tile * NB + (o2 - K * NB);
 }
 
+// Passes of up to three levels are compiled for two resident wavefronts per
+// SIMD (at most 256 registers) and fetch each block right before use; the
+// other wavefront hides that latency.  Four-level passes need the whole SIMD
+// register file for their 16 slots and prefetch one block ahead instead.
+template <int K>
+struct PassTraits {
+  static constexpr bool kPrefetch = K >= 4;
+  static constexpr int kWavesPerEU = K >= 4 ? 1 : 2;
+  static constexpr int kMaxWaves = K >= 4 ? 4 : kWaves;  // wavefronts per workgroup
+};
+
 template <int K, int PREC, bool LI, bool LO>
-__global__ __launch_bounds__(kWaves * 64) void k_fused_pass(FusedArgs a) {
+__global__ __launch_bounds__(PassTraits<K>::kMaxWaves * 64)
+__attribute__((amdgpu_waves_per_eu(PassTraits<K>::kWavesPerEU)))
+void k_fused_pass(FusedArgs a) {
   constexpr int NS = 1 << K;
   constexpr int NB = NS / 2;
   constexpr int NOPS = (LI ? NB : 0) + K * NB + (LO ? NB : 0);
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int n = lane & 31, eta = lane >> 5;
-  const int64_t chunk = (int64_t)blockIdx.y * kWaves + wave;
+  const int64_t chunk = (int64_t)blockIdx.y * (blockDim.x >> 6) + wave;
   if (chunk >= a.nchunks) return;
   const int64_t tile = blockIdx.x;
   const int64_t slo = int64_t(1) << a.log_slo;
@@ -313,13 +326,18 @@ __global__ __launch_bounds__(kWaves * 64) void k_fused_pass(FusedArgs a) {
   // one block operation (op index O) with the next block's operands in flight
   auto step = [&](auto O, const float *x0, const float *x1, float *y0, float *y1) {
     constexpr int o = O;
-    float bs_nxt = 1.f;
-    BlockA nxt;
-    if constexpr (o + 1 < NOPS) nxt = fetch(o + 1, bs_nxt);
-    block_op<PREC>(cur, bs_cur, x0, x0 + 8, x1, x1 + 8, y0, y0 + 8, y1, y1 + 8);
-    if constexpr (o + 1 < NOPS) {
-      cur = nxt;
-      bs_cur = bs_nxt;
+    if constexpr (PassTraits<K>::kPrefetch) {
+      float bs_nxt = 1.f;
+      BlockA nxt;
+      if constexpr (o + 1 < NOPS) nxt = fetch(o + 1, bs_nxt);
+      block_op<PREC>(cur, bs_cur, x0, x0 + 8, x1, x1 + 8, y0, y0 + 8, y1, y1 + 8);
+      if constexpr (o + 1 < NOPS) {
+        cur = nxt;
+        bs_cur = bs_nxt;
+      }
+    } else {
+      if constexpr (o > 0) cur = fetch(o, bs_cur);
+      block_op<PREC>(cur, bs_cur, x0, x0 + 8, x1, x1 + 8, y0, y0 + 8, y1, y1 + 8);
     }
     __builtin_amdgcn_sched_barrier(0);
   };
@@ -393,16 +411,26 @@ __global__ __launch_bounds__(kWaves * 64) void k_fused_pass(FusedArgs a) {
   });
 }
 
+// One workgroup per tile and group of up to kMaxWaves right-hand-side chunks.
+template <int K>
+inline dim3 launch_block(const FusedArgs &a) {
+  const int64_t w = a.nchunks < PassTraits<K>::kMaxWaves ? a.nchunks : PassTraits<K>::kMaxWaves;
+  return dim3((unsigned)(w * 64));
+}
+template <int K>
+inline dim3 launch_grid(const FusedArgs &a) {
+  const int64_t w = a.nchunks < PassTraits<K>::kMaxWaves ? a.nchunks : PassTraits<K>::kMaxWaves;
+  return dim3((unsigned)a.ntiles, (unsigned)((a.nchunks + w - 1) / w));
+}
+
 // Launch one pass of precision PREC (defined in bf_fused_<prec>.hip).
 template <int PREC>
-hipError_t launch_prec(const FusedArgs &a, int K, bool leaf_in, bool leaf_out, dim3 grid,
-                       hipStream_t s);
+hipError_t launch_prec(const FusedArgs &a, int K, bool leaf_in, bool leaf_out, hipStream_t s);
 
 #define BF_FUSED_DEFINE_LAUNCH(PREC)                                                      \
   template <>                                                                             \
-  hipError_t launch_prec<PREC>(const FusedArgs &a, int K, bool li, bool lo, dim3 grid,   \
+  hipError_t launch_prec<PREC>(const FusedArgs &a, int K, bool li, bool lo,              \
                                hipStream_t s) {                                           \
-    const dim3 block(kWaves * 64);                                                        \
     switch (K * 4 + (li ? 2 : 0) + (lo ? 1 : 0)) {                                        \
       BF_FUSED_CASES(1, PREC)                                                             \
       BF_FUSED_CASES(2, PREC)                                                             \
@@ -416,13 +444,16 @@ hipError_t launch_prec(const FusedArgs &a, int K, bool leaf_in, bool leaf_out, d
 
 #define BF_FUSED_CASES(KK, PREC)                                                              \
   case KK * 4 + 0:                                                                            \
-    hipLaunchKernelGGL((k_fused_pass<KK, PREC, false, false>), grid, block, 0, s, a);         \
+    hipLaunchKernelGGL((k_fused_pass<KK, PREC, false, false>), launch_grid<KK>(a),            \
+                       launch_block<KK>(a), 0, s, a);                                         \
     break;                                                                                    \
   case KK * 4 + 2:                                                                            \
-    hipLaunchKernelGGL((k_fused_pass<KK, PREC, true, false>), grid, block, 0, s, a);          \
+    hipLaunchKernelGGL((k_fused_pass<KK, PREC, true, false>), launch_grid<KK>(a),             \
+                       launch_block<KK>(a), 0, s, a);                                         \
     break;                                                                                    \
   case KK * 4 + 1:                                                                            \
-    hipLaunchKernelGGL((k_fused_pass<KK, PREC, false, true>), grid, block, 0, s, a);          \
+    hipLaunchKernelGGL((k_fused_pass<KK, PREC, false, true>), launch_grid<KK>(a),             \
+                       launch_block<KK>(a), 0, s, a);                                         \
     break;
 
 }  // namespace fused

@@ -70,9 +70,9 @@ def test_fused_apply_and_adjoint(dev, fio4096, prec, nrhs, pad):
     assert oracle.rel_err(v, oracle.bf_apply_adjoint(f, g)) < TOL[prec]
 
 
-@pytest.mark.parametrize("kmax", [1, 2, 3])
+@pytest.mark.parametrize("kmax", [1, 2, 3, 4])
 def test_fused_pass_depths_agree(dev, fio4096, kmax):
-    # the same factor product split into passes of 1, 2 or 3 levels
+    # the same factor product split into passes of 1 to 4 levels
     g = complex_gaussian((4096, 40), 5)
     ref = oracle.bf_apply(fio4096, g)
     h = _handle(fio4096, "f32", kmax=kmax)
