@@ -203,8 +203,8 @@ bf_status ensure_ws(bf_plan *p, size_t bytes) {
 }
 
 size_t act_bytes(const bf_plan *p, int64_t nrhs) {
-  const int64_t nchunks = (nrhs + bfly::kChunk - 1) / bfly::kChunk;
-  return (size_t)bfly::act_elems(p->P, p->r, nchunks) * cplx_bytes(p->prec);
+  const int64_t nchunks = (nrhs + (int64_t(1) << p->cs) - 1) >> p->cs;
+  return (size_t)bfly::act_elems(p->P, p->r, nchunks, p->cs) * cplx_bytes(p->prec);
 }
 
 bf_status check_call(bf_plan *p, const void *in, const void *out, int64_t nrhs, int64_t ld) {

@@ -23,7 +23,7 @@ namespace {
 
 using cd = std::complex<double>;
 
-inline int row_of_h(int eta, int rho) { return rho < 4 ? 4 * eta + rho : 8 + 4 * eta + (rho - 4); }
+inline int row32(int e, int rho) { return rho < 4 ? 4 * e + rho : 8 + 4 * e + (rho - 4); }
 
 inline uint16_t bf16_rne(float x) {
   uint32_t u;
@@ -51,16 +51,30 @@ inline float f16_to_f(uint16_t u) {
 }
 
 // Lay out one 32 x 32 complex block M[o][k] (o = c r + a, k = c' r + b) as the
-// per-lane A operands of block_f32 / block_split.  Returns the FP16 block scale.
-float pack_block(const cd *M, int prec, char *dst) {
+// per-lane A operands of the block products in bf_fused_kernel.h.  Returns the
+// FP16 block scale (1 otherwise).
+float pack_block(const cd *M, int prec, int cols, char *dst) {
+  // A value of K index (part, c', row) for output row o: [Re M, -Im M]
+  auto aval = [&](int o, int part, int cp, int row) {
+    const cd v = M[o * 32 + cp * 16 + row];
+    return part == 0 ? v.real() : -v.imag();
+  };
   if (prec == kF32) {
-    float *o = reinterpret_cast<float *>(dst);
+    float *out = reinterpret_cast<float *>(dst);
     for (int lane = 0; lane < 64; ++lane) {
-      const int i = lane & 31, eta = lane >> 5;
-      for (int s = 0; s < 32; ++s) {
-        const int part = s >> 4, cp = (s >> 3) & 1, rho = s & 7;
-        const cd v = M[i * 32 + cp * 16 + row_of_h(eta, rho)];
-        o[((s >> 2) * 64 + lane) * 4 + (s & 3)] = (float)(part == 0 ? v.real() : -v.imag());
+      if (cols == 32) {
+        const int i = lane & 31, e = lane >> 5;
+        for (int s = 0; s < 32; ++s)
+          out[((s >> 2) * 64 + lane) * 4 + (s & 3)] =
+              (float)aval(i, s >> 4, (s >> 3) & 1, row32(e, s & 7));
+      } else {
+        const int i = lane & 15, e = lane >> 4;
+        for (int T = 0; T < 2; ++T)
+          for (int s = 0; s < 16; ++s) {
+            const int f = 16 * T + s;
+            out[((f >> 2) * 64 + lane) * 4 + (f & 3)] =
+                (float)aval(16 * T + i, s >> 3, (s >> 2) & 1, 4 * e + (s & 3));
+          }
       }
     }
     return 1.f;
@@ -75,25 +89,30 @@ float pack_block(const cd *M, int prec, char *dst) {
     pre = std::ldexp(1.0, -ex);           // block entries scaled into [0.5, 1)
     bscale = (float)std::ldexp(1.0, ex);  // undone on the accumulator
   }
-  uint16_t *o = reinterpret_cast<uint16_t *>(dst);
+  uint16_t *out = reinterpret_cast<uint16_t *>(dst);
+  auto put = [&](int w, int lane, int j, double x) {
+    uint16_t h, l;
+    const float xf = (float)(x * pre);
+    if (prec == kBF16) {
+      h = bf16_rne(xf);
+      l = bf16_rne(xf - bf16_to_f(h));
+    } else {
+      h = f16_rne(xf);
+      l = f16_rne(xf - f16_to_f(h));
+    }
+    out[((w * 64) + lane) * 8 + j] = h;
+    out[(((4 + w) * 64) + lane) * 8 + j] = l;
+  };
   for (int lane = 0; lane < 64; ++lane) {
-    const int i = lane & 31, eta = lane >> 5;
-    for (int t = 0; t < 4; ++t) {
-      const int part = t >> 1, cp = t & 1;
-      for (int j = 0; j < 8; ++j) {
-        const cd v = M[i * 32 + cp * 16 + row_of_h(eta, j)];
-        const float x = (float)((part == 0 ? v.real() : -v.imag()) * pre);
-        uint16_t h, l;
-        if (prec == kBF16) {
-          h = bf16_rne(x);
-          l = bf16_rne(x - bf16_to_f(h));
-        } else {
-          h = f16_rne(x);
-          l = f16_rne(x - f16_to_f(h));
-        }
-        o[((t * 64) + lane) * 8 + j] = h;
-        o[(((4 + t) * 64) + lane) * 8 + j] = l;
-      }
+    if (cols == 32) {
+      const int i = lane & 31, e = lane >> 5;
+      for (int t = 0; t < 4; ++t)
+        for (int j = 0; j < 8; ++j) put(t, lane, j, aval(i, t >> 1, t & 1, row32(e, j)));
+    } else {
+      const int i = lane & 15, e = lane >> 4;
+      for (int T = 0; T < 2; ++T)
+        for (int t = 0; t < 2; ++t)
+          for (int j = 0; j < 8; ++j) put(2 * T + t, lane, j, aval(16 * T + i, t, j >> 2, 4 * e + (j & 3)));
     }
   }
   return bscale;
@@ -102,7 +121,7 @@ float pack_block(const cd *M, int prec, char *dst) {
 }  // namespace
 
 struct FusedPass {
-  int K = 0, log_slo = 0, mode_si = 1, in_kind = kInAct, out_kind = kOutAct;
+  int K = 0, cols = 32, log_slo = 0, mode_si = 1, in_kind = kInAct, out_kind = kOutAct;
   int64_t ntiles = 0;
   void *fac = nullptr, *leaf = nullptr;
   float *fscale = nullptr, *lscale = nullptr;
@@ -238,13 +257,14 @@ bf_status upload(bf_plan *p, FusedPass *fp, const void *src, size_t bytes, void 
   return BF_OK;
 }
 
-bf_status build_pass(bf_plan *p, const HostFactors &F, const PassPlan &pp, int prec,
+bf_status build_pass(bf_plan *p, const HostFactors &F, const PassPlan &pp, int prec, int cols,
                      const float *Sm, FusedPass **out) {
   FusedPass *fp = new FusedPass();
   *out = fp;
   const int K = pp.K, L = p->L;
   const int NB = 1 << (K - 1);
   fp->K = K;
+  fp->cols = cols;
   fp->log_slo = L - pp.l_hi;
   fp->mode_si = (pp.side == kHfwd || pp.side == kGadj) ? 1 : 0;
   fp->in_kind = pp.in_kind;
@@ -267,7 +287,7 @@ bf_status build_pass(bf_plan *p, const HostFactors &F, const PassPlan &pp, int p
           const int beta = ap * (1 << d) + b;
           const int64_t bi = ((int64_t)d * ntiles + tile) * NB + beta;
           butterfly_block(F, pp, d, hi, lo, ap, b, M.data());
-          sc[bi] = pack_block(M.data(), prec, buf.data() + bi * kBlockBytes);
+          sc[bi] = pack_block(M.data(), prec, cols, buf.data() + bi * kBlockBytes);
         }
   });
   bf_status st = upload(p, fp, buf.data(), buf.size(), &fp->fac);
@@ -286,7 +306,7 @@ bf_status build_pass(bf_plan *p, const HostFactors &F, const PassPlan &pp, int p
       for (int q = 0; q < NB; ++q) {
         const int64_t bi = tile * NB + q;
         leaf_block(F, use_v, in, (tile << K) + 2 * q, M.data());
-        ls[bi] = pack_block(M.data(), prec, lb.data() + bi * kBlockBytes);
+        ls[bi] = pack_block(M.data(), prec, cols, lb.data() + bi * kBlockBytes);
       }
     });
     st = upload(p, fp, lb.data(), lb.size(), &fp->leaf);
@@ -308,7 +328,7 @@ hipError_t launch_pass(const bf_plan *p, const FusedPass *fp, const void *in, vo
   a.Sm = fp->Sm;
   a.ld = ld;
   a.nrhs = nrhs;
-  a.nchunks = (nrhs + kChunk - 1) / kChunk;
+  a.nchunks = (nrhs + fp->cols - 1) / fp->cols;
   a.nslots = p->P;
   a.ntiles = fp->ntiles;
   a.m = p->m;
@@ -316,10 +336,13 @@ hipError_t launch_pass(const bf_plan *p, const FusedPass *fp, const void *in, vo
   a.mode_si = fp->mode_si;
   a.in_kind = fp->in_kind;
   a.out_kind = fp->out_kind;
+  a.ngroups = 1;
+  a.log_m = 0;
+  while ((int64_t(1) << a.log_m) < a.m) ++a.log_m;
   const bool li = fp->in_kind == kInUser, lo = fp->out_kind == kOutUser;
-  if (p->prec == BF_PREC_F32) return launch_prec<kF32>(a, fp->K, li, lo, s);
-  if (p->prec == BF_PREC_SPLIT_BF16) return launch_prec<kBF16>(a, fp->K, li, lo, s);
-  return launch_prec<kF16>(a, fp->K, li, lo, s);
+  if (p->prec == BF_PREC_F32) return launch_prec<kF32>(a, fp->cols, fp->K, li, lo, s);
+  if (p->prec == BF_PREC_SPLIT_BF16) return launch_prec<kBF16>(a, fp->cols, fp->K, li, lo, s);
+  return launch_prec<kF16>(a, fp->cols, fp->K, li, lo, s);
 }
 
 }  // namespace
@@ -331,8 +354,16 @@ bool fused_supported(const bf_shape &sh, bf_precision prec) {
 
 bf_status fused_build(bf_plan *p, const bf_factors_host *f) {
   HostFactors F{f, p->L, p->h};
-  int kmax = kDefaultK;
-  if (const char *e = std::getenv("BF_FUSED_KMAX")) kmax = std::max(1, std::min(kMaxK, std::atoi(e)));
+  // wavefront geometry (columns per wavefront) and deepest pass; environment
+  // overrides exist for measurements
+  int cols = kDefaultCols;
+  if (const char *e = std::getenv("BF_FUSED_COLS")) cols = std::atoi(e) == 32 ? 32 : 16;
+  const int kcap = cols == 32 ? 3 : 4;
+  // FP32 passes are MFMA-bound and keep their best MFMA utilisation at three
+  // levels; split-precision passes are HBM-bound and gain from four (fewer passes)
+  int kmax = std::min(kcap, prec == kF32 ? 3 : 4);
+  if (const char *e = std::getenv("BF_FUSED_KMAX")) kmax = std::max(1, std::min(kcap, std::atoi(e)));
+  p->cs = cols == 32 ? 5 : 4;
   const int prec = p->prec == BF_PREC_F32 ? kF32 : p->prec == BF_PREC_SPLIT_BF16 ? kBF16 : kF16;
 
   // middle weights as FP32 in natural slot order: S for the forward, S^T for the adjoint
@@ -361,7 +392,7 @@ bf_status fused_build(bf_plan *p, const bf_factors_host *f) {
     for (size_t t = 0; t < ks.size(); ++t) {
       PassPlan pp{adj ? kGadj : kHfwd, ks[t], l_hi, l_hi - ks[t], t == 0 ? kInUser : kInAct, kOutAct};
       FusedPass *fp = nullptr;
-      st = build_pass(p, F, pp, prec, nullptr, &fp);
+      st = build_pass(p, F, pp, prec, cols, nullptr, &fp);
       list.push_back(fp);
       if (st != BF_OK) return st;
       l_hi -= ks[t];
@@ -373,7 +404,7 @@ bf_status fused_build(bf_plan *p, const bf_factors_host *f) {
       PassPlan pp{adj ? kHadj : kGfwd, K, l_lo + K, l_lo, t == 0 ? kInMiddle : kInAct,
                   t + 1 == ks.size() ? kOutUser : kOutAct};
       FusedPass *fp = nullptr;
-      st = build_pass(p, F, pp, prec, t == 0 ? (const float *)(adj ? dST : dS) : nullptr, &fp);
+      st = build_pass(p, F, pp, prec, cols, t == 0 ? (const float *)(adj ? dST : dS) : nullptr, &fp);
       list.push_back(fp);
       if (st != BF_OK) return st;
       l_lo += K;

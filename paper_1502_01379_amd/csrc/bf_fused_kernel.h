@@ -2,27 +2,28 @@
 //
 // A pass applies K consecutive butterfly levels (plus, at the ends of the
 // product, the leaf blocks or the middle weights) to one tile of 2^K slots.
-// One wavefront owns 32 right-hand-side columns of the tile and keeps all of
-// its 2^K slots in registers for the whole pass:
+// One wavefront owns COLS right-hand-side columns of the tile and keeps all of
+// its 2^K slots in registers for the whole pass.  Two lane geometries:
 //
-//   lane l: column n = l % 32 of the chunk, half eta = l / 32;
-//   slot q: 8 complex rows per lane, rows {4 eta .. 4 eta + 3, 8 + 4 eta .. 11 + 4 eta}
-//           of the slot's r = 16 coefficients.
+//   COLS = 32 (v_mfma_*_32x32):  lane l -> column l % 32, half e = l / 32;
+//            the lane holds slot rows {4e..4e+3, 8+4e..11+4e} (8 complex).
+//   COLS = 16 (v_mfma_*_16x16):  lane l -> column l % 16, quarter e = l / 16;
+//            the lane holds slot rows {4e..4e+3} (4 complex).
 //
 // A butterfly (two input slots -> two output slots, one 32 x 32 complex block;
 // Sec. 3.2.1 and 3.2.2: G^l_{2i+c,j} acting on [z_{i,2j}; z_{i,2j+1}], and the
-// H analogue) is two real 32 x 32 x 64 products on the matrix cores:
+// H analogue) is computed as real contractions on the matrix cores:
 //   Re(out) = [Re M, -Im M] . [Re x; Im x],  Im(out) = [Re M, -Im M] . [Im x; -Re x].
-// The 32 x 32 accumulator of v_mfma_*_32x32 leaves, in each lane, exactly the
-// rows that the next level's B operand needs from that lane, so the
-// interleaving of slots between levels is register renaming: no LDS, no
-// cross-lane traffic.  The A operands (the blocks) are packed on the host in
-// per-lane order, 8 KB per block, streamed through L2 one block ahead of use.
+// The accumulator layout of one level holds, in each lane, exactly the rows
+// that the next level's B operand needs from that lane, so the interleaving of
+// slots between levels is register renaming: no LDS, no cross-lane traffic.
+// The A operands (the blocks) are packed on the host in per-lane order, 8 KB
+// per block, and read through L2 (every wavefront of a tile reads the same
+// blocks).
 //
-// Precisions: FP32 (v_mfma_f32_32x32x2_f32), and split BF16 / FP16
-// (x = hi + lo, three v_mfma_f32_32x32x16 products lo*hi + hi*lo + hi*hi with
-// FP32 accumulation; FP16 also scales each block and each column by a power
-// of two to stay inside the FP16 range).
+// Precisions: FP32, and split BF16 / FP16 (x = hi + lo, three MFMA products
+// lo*hi + hi*lo + hi*hi with FP32 accumulation; FP16 also scales each block and
+// each column by a power of two to stay inside the FP16 range).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -46,6 +47,7 @@ __device__ __forceinline__ void static_for(F &&f) {
 }
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -54,9 +56,7 @@ typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kRank = 16;          // r == n0 == 16
 constexpr int kBlockBytes = 8192;  // packed A operands of one 32 x 32 complex block
-constexpr int kMaxK = 4;          // deepest compiled pass
-constexpr int kDefaultK = 3;      // deepest pass used unless BF_FUSED_KMAX says otherwise
-constexpr int kWaves = 8;          // most wavefronts (right-hand-side chunks) per workgroup
+constexpr int kDefaultCols = 16;   // columns per wavefront unless BF_FUSED_COLS says otherwise
 
 enum InKind : int { kInAct = 0, kInUser = 1, kInMiddle = 2 };
 enum OutKind : int { kOutAct = 0, kOutUser = 1 };
@@ -71,16 +71,12 @@ struct FusedArgs {
   const float *lscale;  // FP16: same for leaf blocks
   const float *Sm;      // middle weights in natural slot order (kInMiddle)
   int64_t ld, nrhs, nchunks, nslots, ntiles, m;
-  int log_slo, mode_si, in_kind, out_kind;
+  int log_slo, mode_si, in_kind, out_kind, ngroups, log_m;
 };
 
 struct BlockA {
   u32x4 v[8];  // this lane's 128 bytes of one packed block
 };
-
-__device__ __forceinline__ int row_of(int eta, int rho) {
-  return rho < 4 ? 4 * eta + rho : 8 + 4 * eta + (rho - 4);
-}
 
 // Component j of a 4-vector.  The element is copied to a scalar before any
 // reinterpretation: hipcc for gfx950 reads element 0 when __builtin_bit_cast
@@ -99,34 +95,6 @@ __device__ __forceinline__ BlockA load_block(const char *A, int lane) {
 #pragma unroll
   for (int v = 0; v < 8; ++v) b.v[v] = p[v * 64];
   return b;
-}
-
-// ---- one 32 x 32 complex block: (x0, x1) -> (y0, y1) ---------------------------
-__device__ __forceinline__ void block_f32(const BlockA &A, const float *x0r, const float *x0i,
-                                          const float *x1r, const float *x1i, float *y0r,
-                                          float *y0i, float *y1r, float *y1i) {
-  floatx16 dr = {}, di = {};
-#pragma unroll
-  for (int s = 0; s < 32; ++s) {
-    const float a = as_f32(A.v[s >> 2], s & 3);
-    const int part = s >> 4, cp = (s >> 3) & 1, rho = s & 7;
-    const float xre = cp ? x1r[rho] : x0r[rho];
-    const float xim = cp ? x1i[rho] : x0i[rho];
-    if (part == 0) {
-      dr = __builtin_amdgcn_mfma_f32_32x32x2f32(a, xre, dr, 0, 0, 0);
-      di = __builtin_amdgcn_mfma_f32_32x32x2f32(a, xim, di, 0, 0, 0);
-    } else {
-      dr = __builtin_amdgcn_mfma_f32_32x32x2f32(a, xim, dr, 0, 0, 0);
-      di = __builtin_amdgcn_mfma_f32_32x32x2f32(a, -xre, di, 0, 0, 0);
-    }
-  }
-#pragma unroll
-  for (int rho = 0; rho < 8; ++rho) {
-    y0r[rho] = dr[rho];
-    y1r[rho] = dr[8 + rho];
-    y0i[rho] = di[rho];
-    y1i[rho] = di[8 + rho];
-  }
 }
 
 template <class H8, class Hs>
@@ -148,138 +116,332 @@ __device__ __forceinline__ H8 neg8(const H8 &x) {
   return __builtin_bit_cast(H8, u);
 }
 
-__device__ __forceinline__ floatx16 mfma16(const bf16x8 &a, const bf16x8 &b, floatx16 c) {
+__device__ __forceinline__ floatx16 mfma32(const bf16x8 &a, const bf16x8 &b, floatx16 c) {
   return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
 }
-__device__ __forceinline__ floatx16 mfma16(const halfx8 &a, const halfx8 &b, floatx16 c) {
+__device__ __forceinline__ floatx16 mfma32(const halfx8 &a, const halfx8 &b, floatx16 c) {
   return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
 }
+__device__ __forceinline__ floatx4 mfma16(const bf16x8 &a, const bf16x8 &b, floatx4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ floatx4 mfma16(const halfx8 &a, const halfx8 &b, floatx4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+}
 
-// Split precision: K step t = 2 part + c' covers the 8 rows of input slot c' in
-// this lane (part 0: real parts, part 1: imaginary parts).  A.v[t] holds the hi
-// halves of step t, A.v[4 + t] the lo halves.
+// Power-of-two scale for one column from this lane's values and the lanes
+// holding the other rows of the same column.
+template <int COLS>
+__device__ __forceinline__ void column_scale(float mx, float bscale, float &cs, float &inv) {
+  mx = fmaxf(mx, __shfl_xor(mx, 32));
+  if (COLS == 16) mx = fmaxf(mx, __shfl_xor(mx, 16));
+  int e = 0;
+  if (mx > 0.f) (void)frexpf(mx, &e);
+  cs = ldexpf(1.f, -e);
+  inv = ldexpf(bscale, e);
+}
+
+// ---- COLS = 32: slot = x[16] (8 real parts, 8 imaginary parts) ------------------
+//
+// FP32, v_mfma_f32_32x32x2_f32: K step s = 16 part + 8 c' + rho takes row
+// row_of(e, rho) of input slot c' from this lane (part 0: real, 1: imaginary);
+// the A value for lane (i, e) is [Re M, -Im M][i][that K index].
+// Split, v_mfma_f32_32x32x16: K step t = 2 part + c' takes the 8 rows of input
+// slot c' in this lane; A.v[t] holds the hi halves, A.v[4 + t] the lo halves.
+__device__ __forceinline__ void block32_f32(const BlockA &A, const float *x0, const float *x1,
+                                            float *y0, float *y1) {
+  floatx16 dr = {}, di = {};
+#pragma unroll
+  for (int s = 0; s < 32; ++s) {
+    const float a = as_f32(A.v[s >> 2], s & 3);
+    const int part = s >> 4, cp = (s >> 3) & 1, rho = s & 7;
+    const float *x = cp ? x1 : x0;
+    const float xre = x[rho], xim = x[8 + rho];
+    if (part == 0) {
+      dr = __builtin_amdgcn_mfma_f32_32x32x2f32(a, xre, dr, 0, 0, 0);
+      di = __builtin_amdgcn_mfma_f32_32x32x2f32(a, xim, di, 0, 0, 0);
+    } else {
+      dr = __builtin_amdgcn_mfma_f32_32x32x2f32(a, xim, dr, 0, 0, 0);
+      di = __builtin_amdgcn_mfma_f32_32x32x2f32(a, -xre, di, 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int rho = 0; rho < 8; ++rho) {
+    y0[rho] = dr[rho];
+    y1[rho] = dr[8 + rho];
+    y0[8 + rho] = di[rho];
+    y1[8 + rho] = di[8 + rho];
+  }
+}
+
 template <class H8, class Hs, bool kScale>
-__device__ __forceinline__ void block_split(const BlockA &A, float bscale, const float *x0r,
-                                            const float *x0i, const float *x1r,
-                                            const float *x1i, float *y0r, float *y0i, float *y1r,
-                                            float *y1i) {
+__device__ __forceinline__ void block32_split(const BlockA &A, float bscale, const float *x0,
+                                              const float *x1, float *y0, float *y1) {
   float cs = 1.f, inv = 1.f;
   if (kScale) {
-    // per-column power-of-two scale over both halves of the column
     float mx = 0.f;
 #pragma unroll
-    for (int j = 0; j < 8; ++j)
-      mx = fmaxf(mx, fmaxf(fmaxf(fabsf(x0r[j]), fabsf(x0i[j])), fmaxf(fabsf(x1r[j]), fabsf(x1i[j]))));
-    mx = fmaxf(mx, __shfl_xor(mx, 32));
-    int e = 0;
-    if (mx > 0.f) (void)frexpf(mx, &e);
-    cs = ldexpf(1.f, -e);
-    inv = ldexpf(bscale, e);
+    for (int j = 0; j < 16; ++j) mx = fmaxf(mx, fmaxf(fabsf(x0[j]), fabsf(x1[j])));
+    column_scale<32>(mx, bscale, cs, inv);
   }
   H8 xh[4], xl[4];
-  split8<H8, Hs>(x0r, cs, xh[0], xl[0]);
-  split8<H8, Hs>(x1r, cs, xh[1], xl[1]);
-  split8<H8, Hs>(x0i, cs, xh[2], xl[2]);
-  split8<H8, Hs>(x1i, cs, xh[3], xl[3]);
+  split8<H8, Hs>(x0, cs, xh[0], xl[0]);      // t = 0: real parts of slot 0
+  split8<H8, Hs>(x1, cs, xh[1], xl[1]);      // t = 1: real parts of slot 1
+  split8<H8, Hs>(x0 + 8, cs, xh[2], xl[2]);  // t = 2: imaginary parts of slot 0
+  split8<H8, Hs>(x1 + 8, cs, xh[3], xl[3]);  // t = 3: imaginary parts of slot 1
   floatx16 dr = {}, di = {};
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
     const H8 ahi = __builtin_bit_cast(H8, A.v[t]);
     const H8 alo = __builtin_bit_cast(H8, A.v[4 + t]);
-    dr = mfma16(alo, xh[t], dr);
-    dr = mfma16(ahi, xl[t], dr);
-    dr = mfma16(ahi, xh[t], dr);
+    dr = mfma32(alo, xh[t], dr);
+    dr = mfma32(ahi, xl[t], dr);
+    dr = mfma32(ahi, xh[t], dr);
     const H8 yh = t < 2 ? xh[t + 2] : neg8(xh[t - 2]);
     const H8 yl = t < 2 ? xl[t + 2] : neg8(xl[t - 2]);
-    di = mfma16(alo, yh, di);
-    di = mfma16(ahi, yl, di);
-    di = mfma16(ahi, yh, di);
+    di = mfma32(alo, yh, di);
+    di = mfma32(ahi, yl, di);
+    di = mfma32(ahi, yh, di);
   }
 #pragma unroll
   for (int rho = 0; rho < 8; ++rho) {
-    y0r[rho] = dr[rho] * inv;
-    y1r[rho] = dr[8 + rho] * inv;
-    y0i[rho] = di[rho] * inv;
-    y1i[rho] = di[8 + rho] * inv;
+    y0[rho] = dr[rho] * inv;
+    y1[rho] = dr[8 + rho] * inv;
+    y0[8 + rho] = di[rho] * inv;
+    y1[8 + rho] = di[8 + rho] * inv;
   }
 }
 
-template <int PREC>
-__device__ __forceinline__ void block_op(const BlockA &A, float bscale, const float *x0r,
-                                         const float *x0i, const float *x1r, const float *x1i,
-                                         float *y0r, float *y0i, float *y1r, float *y1i) {
-  if constexpr (PREC == kF32)
-    block_f32(A, x0r, x0i, x1r, x1i, y0r, y0i, y1r, y1i);
-  else if constexpr (PREC == kBF16)
-    block_split<bf16x8, __bf16, false>(A, 1.f, x0r, x0i, x1r, x1i, y0r, y0i, y1r, y1i);
-  else
-    block_split<halfx8, _Float16, true>(A, bscale, x0r, x0i, x1r, x1i, y0r, y0i, y1r, y1i);
+// ---- COLS = 16: slot = x[8] (4 real parts, 4 imaginary parts) -------------------
+//
+// Output tile T (16 rows) is output slot c = T.
+// FP32, v_mfma_f32_16x16x4_f32: K step s = 8 part + 4 c' + rho takes row 4e + rho
+// of input slot c'; A value for lane (i, e): [Re M, -Im M][16T + i][that K index],
+// stored at float index 16 T + s of the lane's 32.
+// Split, v_mfma_f32_16x16x32: K step t = part; this lane's 8 values are rows
+// 4e..4e+3 of slot 0 then of slot 1; A.v[2T + t] hi, A.v[4 + 2T + t] lo.
+__device__ __forceinline__ void block16_f32(const BlockA &A, const float *x0, const float *x1,
+                                            float *y0, float *y1) {
+  floatx4 dr[2] = {{}, {}}, di[2] = {{}, {}};
+#pragma unroll
+  for (int s = 0; s < 16; ++s) {
+    const int part = s >> 3, cp = (s >> 2) & 1, rho = s & 3;
+    const float *x = cp ? x1 : x0;
+    const float xre = x[rho], xim = x[4 + rho];
+#pragma unroll
+    for (int T = 0; T < 2; ++T) {
+      const int f = 16 * T + s;
+      const float a = as_f32(A.v[f >> 2], f & 3);
+      if (part == 0) {
+        dr[T] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, xre, dr[T], 0, 0, 0);
+        di[T] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, xim, di[T], 0, 0, 0);
+      } else {
+        dr[T] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, xim, dr[T], 0, 0, 0);
+        di[T] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, -xre, di[T], 0, 0, 0);
+      }
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    y0[v] = dr[0][v];
+    y0[4 + v] = di[0][v];
+    y1[v] = dr[1][v];
+    y1[4 + v] = di[1][v];
+  }
 }
 
-// Block operands in the order the pass consumes them: leaf-in pairs, then
-// depth 0 .. K-1 butterflies, then leaf-out pairs.
-template <int K, bool LI>
-__device__ __forceinline__ int64_t op_block(const FusedArgs &a, int64_t tile, int o,
-                                            const char *&base_ptr, const float *&scale_ptr) {
-  constexpr int NB = 1 << (K - 1);
-  if (LI && o < NB) {
-    base_ptr = a.leaf;
-    scale_ptr = a.lscale;
-    return tile * NB + o;
+template <class H8, class Hs, bool kScale>
+__device__ __forceinline__ void block16_split(const BlockA &A, float bscale, const float *x0,
+                                              const float *x1, float *y0, float *y1) {
+  float cs = 1.f, inv = 1.f;
+  if (kScale) {
+    float mx = 0.f;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) mx = fmaxf(mx, fmaxf(fabsf(x0[j]), fabsf(x1[j])));
+    column_scale<16>(mx, bscale, cs, inv);
   }
-  const int o2 = o - (LI ? NB : 0);
-  if (o2 < K * NB) {
-    base_ptr = a.fac;
-    scale_ptr = a.fscale;
-    return ((int64_t)(o2 / NB) * a.ntiles + tile) * NB + (o2 % NB);
+  float re[8], im[8];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    re[j] = x0[j];
+    re[4 + j] = x1[j];
+    im[j] = x0[4 + j];
+    im[4 + j] = x1[4 + j];
   }
-  base_ptr = a.leaf;
-  scale_ptr = a.lscale;
-  return tile * NB + (o2 - K * NB);
+  H8 xh[2], xl[2];
+  split8<H8, Hs>(re, cs, xh[0], xl[0]);
+  split8<H8, Hs>(im, cs, xh[1], xl[1]);
+  const H8 nh = neg8(xh[0]), nl = neg8(xl[0]);
+  floatx4 dr[2] = {{}, {}}, di[2] = {{}, {}};
+#pragma unroll
+  for (int T = 0; T < 2; ++T) {
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const H8 ahi = __builtin_bit_cast(H8, A.v[2 * T + t]);
+      const H8 alo = __builtin_bit_cast(H8, A.v[4 + 2 * T + t]);
+      dr[T] = mfma16(alo, xh[t], dr[T]);
+      dr[T] = mfma16(ahi, xl[t], dr[T]);
+      dr[T] = mfma16(ahi, xh[t], dr[T]);
+      const H8 yh = t == 0 ? xh[1] : nh;
+      const H8 yl = t == 0 ? xl[1] : nl;
+      di[T] = mfma16(alo, yh, di[T]);
+      di[T] = mfma16(ahi, yl, di[T]);
+      di[T] = mfma16(ahi, yh, di[T]);
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    y0[v] = dr[0][v] * inv;
+    y0[4 + v] = di[0][v] * inv;
+    y1[v] = dr[1][v] * inv;
+    y1[4 + v] = di[1][v] * inv;
+  }
 }
 
-// Passes of up to three levels are compiled for two resident wavefronts per
-// SIMD (at most 256 registers) and fetch each block right before use; the
-// other wavefront hides that latency.  Four-level passes need the whole SIMD
-// register file for their 16 slots and prefetch one block ahead instead.
-template <int K>
-struct PassTraits {
-  static constexpr bool kPrefetch = K >= 4;
-  static constexpr int kWavesPerEU = K >= 4 ? 1 : 2;
-  static constexpr int kMaxWaves = K >= 4 ? 4 : kWaves;  // wavefronts per workgroup
+template <int COLS, int PREC>
+__device__ __forceinline__ void block_op(const BlockA &A, float bscale, const float *x0,
+                                         const float *x1, float *y0, float *y1) {
+  if constexpr (COLS == 32) {
+    if constexpr (PREC == kF32)
+      block32_f32(A, x0, x1, y0, y1);
+    else if constexpr (PREC == kBF16)
+      block32_split<bf16x8, __bf16, false>(A, 1.f, x0, x1, y0, y1);
+    else
+      block32_split<halfx8, _Float16, true>(A, bscale, x0, x1, y0, y1);
+  } else {
+    if constexpr (PREC == kF32)
+      block16_f32(A, x0, x1, y0, y1);
+    else if constexpr (PREC == kBF16)
+      block16_split<bf16x8, __bf16, false>(A, 1.f, x0, x1, y0, y1);
+    else
+      block16_split<halfx8, _Float16, true>(A, bscale, x0, x1, y0, y1);
+  }
+}
+
+// ---- geometry: which slot rows a lane holds ----------------------------------------
+template <int COLS>
+struct Geo;
+template <>
+struct Geo<32> {
+  static constexpr int kSW = 16;  // floats per slot per lane
+  static constexpr int kRows = 8;
+  __device__ static int row(int e, int rho) { return rho < 4 ? 4 * e + rho : 8 + 4 * e + (rho - 4); }
+  // activation pair j (rows 2 pair, 2 pair + 1) held by this lane
+  __device__ static int pair(int e, int j) { return (j < 2) ? 2 * e + j : 4 + 2 * e + (j - 2); }
+};
+template <>
+struct Geo<16> {
+  static constexpr int kSW = 8;
+  static constexpr int kRows = 4;
+  __device__ static int row(int e, int rho) { return 4 * e + rho; }
+  __device__ static int pair(int e, int j) { return 2 * e + j; }
 };
 
-template <int K, int PREC, bool LI, bool LO>
-__global__ __launch_bounds__(PassTraits<K>::kMaxWaves * 64)
-__attribute__((amdgpu_waves_per_eu(PassTraits<K>::kWavesPerEU)))
+// Launch shape per pass depth.  Every pass fits two resident wavefronts per
+// SIMD (at most 256 registers).  Blocks are staged in LDS in groups of
+// kStageBlocks (double buffered, 2 x kStageBlocks x 8 KB); four-level passes
+// use half-level stages and four-wavefront workgroups so that two workgroups
+// share a CU and overlap each other's loads and stores.
+template <int COLS, int K>
+struct PassTraits {
+  static constexpr int kWavesPerEU = 2;
+  static constexpr int kMaxWaves = K >= 4 ? 4 : 8;  // wavefronts per workgroup
+  static constexpr int kStageBlocks = (1 << (K - 1)) < 4 ? (1 << (K - 1)) : 4;
+};
+
+// Block index of block beta (0 .. 2^(K-1) - 1) of block group g: leaf-in (if
+// LI), levels 0 .. K-1, leaf-out (if LO).
+template <int K, bool LI>
+__device__ __forceinline__ int64_t group_block(const FusedArgs &a, int64_t tile, int g, int beta,
+                                               const char *&base_ptr, const float *&scale_ptr) {
+  constexpr int NB = 1 << (K - 1);
+  const int d = g - (LI ? 1 : 0);
+  if (d < 0 || d >= K) {
+    base_ptr = a.leaf;
+    scale_ptr = a.lscale;
+    return tile * NB + beta;
+  }
+  base_ptr = a.fac;
+  scale_ptr = a.fscale;
+  return ((int64_t)d * a.ntiles + tile) * NB + beta;
+}
+
+// Workgroup -> (tile, group of column chunks).  Workgroups are dispatched to the
+// eight XCDs round robin, so the groups of one tile are placed eight ids apart:
+// they run on the same XCD at about the same time and share its L2.
+__device__ __forceinline__ void tile_of_block(const FusedArgs &a, int64_t &tile, int64_t &group) {
+  const int64_t gid = blockIdx.x;
+  const int64_t G = a.ngroups;
+  if (G == 1) {
+    tile = gid;
+    group = 0;
+  } else if ((a.ntiles & 7) == 0) {
+    const int64_t xcd = gid & 7, r = gid >> 3;
+    group = r % G;
+    tile = (r / G) * 8 + xcd;
+  } else {
+    tile = gid / G;
+    group = gid - tile * G;
+  }
+}
+
+template <int COLS, int K, int PREC, bool LI, bool LO>
+__global__ __launch_bounds__((PassTraits<COLS, K>::kMaxWaves * 64))
+__attribute__((amdgpu_waves_per_eu(PassTraits<COLS, K>::kWavesPerEU)))
 void k_fused_pass(FusedArgs a) {
+  using G = Geo<COLS>;
+  constexpr int SW = G::kSW;
+  constexpr int NR = G::kRows;
   constexpr int NS = 1 << K;
   constexpr int NB = NS / 2;
-  constexpr int NOPS = (LI ? NB : 0) + K * NB + (LO ? NB : 0);
+  constexpr int LOGC = COLS == 32 ? 5 : 4;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int n = lane & 31, eta = lane >> 5;
-  const int64_t chunk = (int64_t)blockIdx.y * (blockDim.x >> 6) + wave;
+  const int n = lane & (COLS - 1), e = lane / COLS;
+  int64_t tile, group;
+  tile_of_block(a, tile, group);
+  const int64_t chunk = group * (blockDim.x >> 6) + wave;
   if (chunk >= a.nchunks) return;
-  const int64_t tile = blockIdx.x;
   const int64_t slo = int64_t(1) << a.log_slo;
   const int64_t hi = tile >> a.log_slo, lo = tile & (slo - 1);
   const int64_t base = hi << (K + a.log_slo);
-  const int64_t col = chunk * 32 + n;
+  const int64_t col = (chunk << LOGC) + n;
   const bool col_ok = col < a.nrhs;
 
-  auto fetch = [&](int o, float &bs) {
+  // Blocks of the stage being computed sit in one half of an LDS double buffer
+  // while the next stage's blocks stream into the other half: every wavefront
+  // of the workgroup copies its share with global -> LDS loads (16 bytes per
+  // lane, no registers), one stage ahead.  Stage st = group g (leaf-in, a
+  // level, leaf-out) times part: blocks part*HB .. part*HB + HB - 1 of g.
+  constexpr int HB = PassTraits<COLS, K>::kStageBlocks;
+  constexpr int NPART = NB / HB;
+  constexpr int NST = ((LI ? 1 : 0) + K + (LO ? 1 : 0)) * NPART;
+  __shared__ __attribute__((aligned(16))) char lds[2 * HB * kBlockBytes];
+  const int W = (int)(blockDim.x >> 6);
+  const int wact = (int)((a.nchunks - group * W) < W ? (a.nchunks - group * W) : W);
+  auto issue_stage = [&](int sti) {
+    char *dst = lds + (sti & 1) * (HB * kBlockBytes);
+    const int g = sti / NPART, b0 = (sti % NPART) * HB;
+    for (int c = wave; c < HB * 8; c += wact) {
+      const char *bp;
+      const float *sp;
+      const int64_t bi = group_block<K, LI>(a, tile, g, b0 + (c >> 3), bp, sp);
+      const char *src = bp + bi * kBlockBytes + (c & 7) * 1024 + lane * 16;
+      __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)(dst + c * 1024),
+                                       16, 0, 0);
+    }
+  };
+  auto block_scale = [&](int g, int beta) {
+    if constexpr (PREC != kF16) return 1.f;
     const char *bp;
     const float *sp;
-    const int64_t bi = op_block<K, LI>(a, tile, o, bp, sp);
-    bs = (PREC == kF16) ? sp[bi] : 1.f;
-    return load_block(bp + bi * kBlockBytes, lane);
+    const int64_t bi = group_block<K, LI>(a, tile, g, beta, bp, sp);
+    return sp[bi];
   };
-  float bs_cur;
-  BlockA cur = fetch(0, bs_cur);
+  issue_stage(0);
 
-  // st[q][0..7] real, st[q][8..15] imaginary parts of this lane's rows of slot q
-  float st[NS][16];
+  // st[q][0 .. NR-1] real, st[q][NR .. 2 NR - 1] imaginary parts of this lane's rows
+  float st[NS][SW];
 
   // ---- inputs at depth 0
   static_for<NS>([&](auto Q) {
@@ -287,104 +449,103 @@ void k_fused_pass(FusedArgs a) {
     const int64_t slot = a.mode_si ? base + ((int64_t)q << a.log_slo) + lo : base + (lo << K) + q;
     if constexpr (LI) {
       const f32x2 *g = static_cast<const f32x2 *>(a.in);
-      static_for<8>([&](auto RHO) {
+      static_for<NR>([&](auto RHO) {
         constexpr int rho = RHO;
         f32x2 v = {0.f, 0.f};
-        if (col_ok) v = __builtin_nontemporal_load(&g[(slot * kRank + row_of(eta, rho)) * a.ld + col]);
+        if (col_ok) v = __builtin_nontemporal_load(&g[(slot * kRank + G::row(e, rho)) * a.ld + col]);
         st[q][rho] = v.x;
-        st[q][8 + rho] = v.y;
+        st[q][NR + rho] = v.y;
       });
     } else {
-      int64_t src = slot;
-      if (a.in_kind == kInMiddle) {
-        const int64_t sh = slot / a.m;
-        src = (slot - sh * a.m) * a.m + sh;
-      }
-      const f32x4 *p = static_cast<const f32x4 *>(a.in) + ((chunk * a.nslots + src) * 8) * 32 + n;
-      static_for<4>([&](auto J) {
+      // the first pass after the middle level reads the transposed slot (M^h is a
+      // block transpose of the m x m grid of slots; m is a power of two)
+      const int64_t tr = ((slot & (a.m - 1)) << a.log_m) | (slot >> a.log_m);
+      const int64_t src = a.in_kind == kInMiddle ? tr : slot;
+      const f32x4 *p = static_cast<const f32x4 *>(a.in) + ((chunk * a.nslots + src) * 8) * COLS + n;
+      static_for<NR / 2>([&](auto J) {
         constexpr int j = J;
-        const int pair = (j < 2) ? 2 * eta + j : 4 + 2 * eta + (j - 2);
-        const f32x4 v = __builtin_nontemporal_load(p + pair * 32);
+        const f32x4 v = __builtin_nontemporal_load(p + G::pair(e, j) * COLS);
         st[q][2 * j] = v.x;
-        st[q][8 + 2 * j] = v.y;
+        st[q][NR + 2 * j] = v.y;
         st[q][2 * j + 1] = v.z;
-        st[q][8 + 2 * j + 1] = v.w;
+        st[q][NR + 2 * j + 1] = v.w;
       });
-      if (a.in_kind == kInMiddle) {
-        const f32x4 *sp = reinterpret_cast<const f32x4 *>(a.Sm + slot * kRank);
-        const f32x4 s0 = sp[eta], s1 = sp[2 + eta];
-        static_for<8>([&](auto RHO) {
-          constexpr int rho = RHO;
-          const float sc = rho < 4 ? pick4(s0, rho & 3) : pick4(s1, rho & 3);
-          st[q][rho] *= sc;
-          st[q][8 + rho] *= sc;
-        });
-      }
     }
   });
+  // middle weights S^h_{i,j}, in natural slot order, after every load is in flight
+  if (!LI && a.in_kind == kInMiddle) {
+    static_for<NS>([&](auto Q) {
+      constexpr int q = Q;
+      const int64_t slot = a.mode_si ? base + ((int64_t)q << a.log_slo) + lo : base + (lo << K) + q;
+      const f32x4 *sp = reinterpret_cast<const f32x4 *>(a.Sm + slot * kRank);
+      static_for<NR / 4>([&](auto J) {
+        constexpr int j = J;
+        const f32x4 s4 = sp[COLS == 32 ? (j == 0 ? e : 2 + e) : e];
+        static_for<4>([&](auto V) {
+          const float sc = pick4(s4, V);
+          st[q][4 * j + V] *= sc;
+          st[q][NR + 4 * j + V] *= sc;
+        });
+      });
+    });
+  }
 
-  // one block operation (op index O) with the next block's operands in flight
-  auto step = [&](auto O, const float *x0, const float *x1, float *y0, float *y1) {
-    constexpr int o = O;
-    if constexpr (PassTraits<K>::kPrefetch) {
-      float bs_nxt = 1.f;
-      BlockA nxt;
-      if constexpr (o + 1 < NOPS) nxt = fetch(o + 1, bs_nxt);
-      block_op<PREC>(cur, bs_cur, x0, x0 + 8, x1, x1 + 8, y0, y0 + 8, y1, y1 + 8);
-      if constexpr (o + 1 < NOPS) {
-        cur = nxt;
-        bs_cur = bs_nxt;
-      }
-    } else {
-      if constexpr (o > 0) cur = fetch(o, bs_cur);
-      block_op<PREC>(cur, bs_cur, x0, x0 + 8, x1, x1 + 8, y0, y0 + 8, y1, y1 + 8);
-    }
-    __builtin_amdgcn_sched_barrier(0);
+  // one block operation: block beta of group g, staged in LDS
+  auto step = [&](auto G, auto BETA, const float *x0, const float *x1, float *y0, float *y1) {
+    constexpr int g = G, beta = BETA;
+    constexpr int sti = g * NPART + beta / HB;
+    const char *blk = lds + (sti & 1) * (HB * kBlockBytes) + (beta % HB) * kBlockBytes;
+    BlockA A;
+    static_for<8>([&](auto V) {
+      A.v[V] = reinterpret_cast<const u32x4 *>(blk + V * 1024)[lane];
+    });
+    block_op<COLS, PREC>(A, block_scale(g, beta), x0, x1, y0, y1);
   };
-
-  // ---- leaf blocks applied to slot pairs before the first level
-  if constexpr (LI) {
+  // entering stage sti: its blocks have landed in LDS, the previous stage is done
+  // everywhere, and the next stage's copy starts
+  auto stage_begin = [&](auto STI) {
+    constexpr int sti = STI;
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if constexpr (sti + 1 < NST) issue_stage(sti + 1);
+  };
+  auto pair_group = [&](auto G) {
+    constexpr int g = G;
     static_for<NB>([&](auto PP) {
       constexpr int pp = PP;
-      float t0[16], t1[16];
-      step(std::integral_constant<int, pp>{}, st[2 * pp], st[2 * pp + 1], t0, t1);
-      static_for<16>([&](auto J) {
+      if constexpr (pp % HB == 0) stage_begin(std::integral_constant<int, g * NPART + pp / HB>{});
+      float t0[SW], t1[SW];
+      step(G, PP, st[2 * pp], st[2 * pp + 1], t0, t1);
+      static_for<SW>([&](auto J) {
         st[2 * pp][J] = t0[J];
         st[2 * pp + 1][J] = t1[J];
       });
     });
-  }
+  };
+
+  // ---- leaf blocks applied to slot pairs before the first level
+  if constexpr (LI) pair_group(std::integral_constant<int, 0>{});
 
   // ---- K butterfly levels
   static_for<K>([&](auto D) {
     constexpr int d = D;
-    float nx[NS][16];
+    constexpr int g = (LI ? 1 : 0) + d;
+    float nx[NS][SW];
     static_for<NB>([&](auto BETA) {
       constexpr int beta = BETA;
+      if constexpr (beta % HB == 0) stage_begin(std::integral_constant<int, g * NPART + beta / HB>{});
       constexpr int ap = beta >> d, b = beta & ((1 << d) - 1);
       constexpr int qi0 = (2 * ap) * (1 << d) + b, qi1 = (2 * ap + 1) * (1 << d) + b;
       constexpr int qo0 = ap * (2 << d) + 2 * b, qo1 = qo0 + 1;
-      constexpr int o = (LI ? NB : 0) + d * NB + beta;
-      step(std::integral_constant<int, o>{}, st[qi0], st[qi1], nx[qo0], nx[qo1]);
+      step(std::integral_constant<int, g>{}, BETA, st[qi0], st[qi1], nx[qo0], nx[qo1]);
     });
     static_for<NS>([&](auto Q) {
-      static_for<16>([&](auto J) { st[Q][J] = nx[Q][J]; });
+      static_for<SW>([&](auto J) { st[Q][J] = nx[Q][J]; });
     });
   });
 
   // ---- leaf blocks after the last level
-  if constexpr (LO) {
-    static_for<NB>([&](auto PP) {
-      constexpr int pp = PP;
-      constexpr int o = (LI ? NB : 0) + K * NB + pp;
-      float t0[16], t1[16];
-      step(std::integral_constant<int, o>{}, st[2 * pp], st[2 * pp + 1], t0, t1);
-      static_for<16>([&](auto J) {
-        st[2 * pp][J] = t0[J];
-        st[2 * pp + 1][J] = t1[J];
-      });
-    });
-  }
+  if constexpr (LO) pair_group(std::integral_constant<int, (LI ? 1 : 0) + K>{});
 
   // ---- outputs at depth K
   static_for<NS>([&](auto Q) {
@@ -393,68 +554,71 @@ void k_fused_pass(FusedArgs a) {
     if constexpr (LO) {
       if (col_ok) {
         f32x2 *u = static_cast<f32x2 *>(a.out);
-        static_for<8>([&](auto RHO) {
+        static_for<NR>([&](auto RHO) {
           constexpr int rho = RHO;
-          const f32x2 v = {st[q][rho], st[q][8 + rho]};
-          __builtin_nontemporal_store(v, &u[(slot * kRank + row_of(eta, rho)) * a.ld + col]);
+          const f32x2 v = {st[q][rho], st[q][NR + rho]};
+          __builtin_nontemporal_store(v, &u[(slot * kRank + G::row(e, rho)) * a.ld + col]);
         });
       }
     } else {
-      f32x4 *p = static_cast<f32x4 *>(a.out) + ((chunk * a.nslots + slot) * 8) * 32 + n;
-      static_for<4>([&](auto J) {
+      f32x4 *p = static_cast<f32x4 *>(a.out) + ((chunk * a.nslots + slot) * 8) * COLS + n;
+      static_for<NR / 2>([&](auto J) {
         constexpr int j = J;
-        const int pair = (j < 2) ? 2 * eta + j : 4 + 2 * eta + (j - 2);
-        const f32x4 v = {st[q][2 * j], st[q][8 + 2 * j], st[q][2 * j + 1], st[q][8 + 2 * j + 1]};
-        __builtin_nontemporal_store(v, p + pair * 32);
+        const f32x4 v = {st[q][2 * j], st[q][NR + 2 * j], st[q][2 * j + 1], st[q][NR + 2 * j + 1]};
+        __builtin_nontemporal_store(v, p + G::pair(e, j) * COLS);
       });
     }
   });
 }
 
-// One workgroup per tile and group of up to kMaxWaves right-hand-side chunks.
-template <int K>
-inline dim3 launch_block(const FusedArgs &a) {
-  const int64_t w = a.nchunks < PassTraits<K>::kMaxWaves ? a.nchunks : PassTraits<K>::kMaxWaves;
-  return dim3((unsigned)(w * 64));
-}
-template <int K>
-inline dim3 launch_grid(const FusedArgs &a) {
-  const int64_t w = a.nchunks < PassTraits<K>::kMaxWaves ? a.nchunks : PassTraits<K>::kMaxWaves;
-  return dim3((unsigned)a.ntiles, (unsigned)((a.nchunks + w - 1) / w));
+// One workgroup per (tile, group of up to kMaxWaves column chunks).
+template <int COLS, int K>
+inline int64_t waves_per_group(const FusedArgs &a) {
+  const int64_t mw = PassTraits<COLS, K>::kMaxWaves;
+  return a.nchunks < mw ? a.nchunks : mw;
 }
 
-// Launch one pass of precision PREC (defined in bf_fused_<prec>.hip).
+// Launch one pass (defined in bf_fused_<prec>.hip).
 template <int PREC>
-hipError_t launch_prec(const FusedArgs &a, int K, bool leaf_in, bool leaf_out, hipStream_t s);
+hipError_t launch_prec(FusedArgs a, int cols, int K, bool leaf_in, bool leaf_out, hipStream_t s);
 
-#define BF_FUSED_DEFINE_LAUNCH(PREC)                                                      \
-  template <>                                                                             \
-  hipError_t launch_prec<PREC>(const FusedArgs &a, int K, bool li, bool lo,              \
-                               hipStream_t s) {                                           \
-    switch (K * 4 + (li ? 2 : 0) + (lo ? 1 : 0)) {                                        \
-      BF_FUSED_CASES(1, PREC)                                                             \
-      BF_FUSED_CASES(2, PREC)                                                             \
-      BF_FUSED_CASES(3, PREC)                                                             \
-      BF_FUSED_CASES(4, PREC)                                                             \
-      default:                                                                            \
-        return hipErrorInvalidValue;                                                      \
-    }                                                                                     \
-    return hipGetLastError();                                                             \
-  }
+#define BF_FUSED_LAUNCH(COLS, KK, PREC, LI, LO)                                               \
+  do {                                                                                        \
+    const int64_t w = waves_per_group<COLS, KK>(a);                                           \
+    a.ngroups = (int)((a.nchunks + w - 1) / w);                                               \
+    hipLaunchKernelGGL((k_fused_pass<COLS, KK, PREC, LI, LO>),                                \
+                       dim3((unsigned)(a.ntiles * a.ngroups)), dim3((unsigned)(w * 64)), 0, s, \
+                       a);                                                                    \
+  } while (0)
 
-#define BF_FUSED_CASES(KK, PREC)                                                              \
-  case KK * 4 + 0:                                                                            \
-    hipLaunchKernelGGL((k_fused_pass<KK, PREC, false, false>), launch_grid<KK>(a),            \
-                       launch_block<KK>(a), 0, s, a);                                         \
-    break;                                                                                    \
-  case KK * 4 + 2:                                                                            \
-    hipLaunchKernelGGL((k_fused_pass<KK, PREC, true, false>), launch_grid<KK>(a),             \
-                       launch_block<KK>(a), 0, s, a);                                         \
-    break;                                                                                    \
-  case KK * 4 + 1:                                                                            \
-    hipLaunchKernelGGL((k_fused_pass<KK, PREC, false, true>), launch_grid<KK>(a),             \
-                       launch_block<KK>(a), 0, s, a);                                         \
+#define BF_FUSED_CASES(COLS, KK, PREC)                         \
+  case (COLS / 16) * 64 + KK * 4 + 0:                          \
+    BF_FUSED_LAUNCH(COLS, KK, PREC, false, false);             \
+    break;                                                     \
+  case (COLS / 16) * 64 + KK * 4 + 2:                          \
+    BF_FUSED_LAUNCH(COLS, KK, PREC, true, false);              \
+    break;                                                     \
+  case (COLS / 16) * 64 + KK * 4 + 1:                          \
+    BF_FUSED_LAUNCH(COLS, KK, PREC, false, true);              \
     break;
+
+#define BF_FUSED_DEFINE_LAUNCH(PREC)                                                        \
+  template <>                                                                               \
+  hipError_t launch_prec<PREC>(FusedArgs a, int cols, int K, bool li, bool lo,             \
+                               hipStream_t s) {                                             \
+    switch ((cols / 16) * 64 + K * 4 + (li ? 2 : 0) + (lo ? 1 : 0)) {                       \
+      BF_FUSED_CASES(32, 1, PREC)                                                           \
+      BF_FUSED_CASES(32, 2, PREC)                                                           \
+      BF_FUSED_CASES(32, 3, PREC)                                                           \
+      BF_FUSED_CASES(16, 1, PREC)                                                           \
+      BF_FUSED_CASES(16, 2, PREC)                                                           \
+      BF_FUSED_CASES(16, 3, PREC)                                                           \
+      BF_FUSED_CASES(16, 4, PREC)                                                           \
+      default:                                                                              \
+        return hipErrorInvalidValue;                                                        \
+    }                                                                                       \
+    return hipGetLastError();                                                               \
+  }
 
 }  // namespace fused
 }  // namespace bfly

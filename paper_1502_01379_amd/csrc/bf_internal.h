@@ -12,17 +12,16 @@
 namespace bfly {
 
 // Activation layout used by every kernel between launches: right-hand sides are
-// grouped in chunks of 32 (one chunk per wavefront of the fused kernels); a
-// chunk holds, for every slot, its r rows in pairs, each pair stored as 32
-// columns of two interleaved complex values (16 bytes per column in FP32):
-//   element (slot, row, n) -> ((n / 32 * nslots + slot) * ceil(r/2) + row / 2) * 64
-//                             + (n % 32) * 2 + row % 2
+// grouped in chunks of C = 2^cs columns (C = 32 or 16: the columns one
+// wavefront of the fused kernels owns); a chunk holds, for every slot, its r
+// rows in pairs, each pair stored as C columns of two interleaved complex
+// values (16 bytes per column in FP32):
+//   element (slot, row, n) -> ((n / C * nslots + slot) * ceil(r/2) + row / 2) * 2C
+//                             + (n % C) * 2 + row % 2
 // nslots = R^L at every level of the tree (R^l nodes of one tree times R^(L-l)
 // nodes of the other).
-constexpr int kChunk = 32;
-
-inline int64_t act_elems(int64_t nslots, int r, int64_t nchunks) {
-  return nchunks * nslots * ((r + 1) / 2) * 2 * kChunk;
+inline int64_t act_elems(int64_t nslots, int r, int64_t nchunks, int cs) {
+  return nchunks * nslots * ((r + 1) / 2) * (int64_t(2) << cs);
 }
 
 // Slot patterns of one butterfly level.  Butterfly b = hi * blo + lo combines R
@@ -57,6 +56,7 @@ struct bf_plan {
   bf_shape shape{};
   bf_precision prec = BF_PREC_F32;
   int path = 0;  // 0 = per-level kernels, 1 = fused MFMA passes
+  int cs = 5;    // log2 of the activation chunk (columns per wavefront of the fused path)
   int R = 2, n0 = 0, L = 0, r = 0, h = 0;
   int64_t P = 0, m = 0, N = 0;
 

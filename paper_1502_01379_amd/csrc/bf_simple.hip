@@ -36,9 +36,11 @@ template <class C> __device__ __forceinline__ C cmulc(C a, C b) {
 }
 
 // Row-pair layout shared with the fused passes (see bf_internal.h).
-__device__ __forceinline__ int64_t act_off(int64_t slot, int row, int64_t n, int64_t nslots, int r) {
+__device__ __forceinline__ int64_t act_off(int64_t slot, int row, int64_t n, int64_t nslots, int r,
+                                           int cs) {
   const int rp = (r + 1) >> 1;
-  return (((n >> 5) * nslots + slot) * rp + (row >> 1)) * (2 * kChunk) + (n & 31) * 2 + (row & 1);
+  return (((n >> cs) * nslots + slot) * rp + (row >> 1)) * (int64_t(2) << cs) +
+         (n & ((1 << cs) - 1)) * 2 + (row & 1);
 }
 
 __device__ __forceinline__ int64_t slot_of(int64_t b, int c, int64_t blo, int R, bool strided) {
@@ -52,7 +54,7 @@ template <class T>
 __global__ void k_leaf_in(const typename Cx<T>::type *__restrict__ W,
                           const typename Cx<T>::type *__restrict__ x, int64_t ld,
                           typename Cx<T>::type *__restrict__ y, int64_t P, int n0, int r,
-                          int64_t nrhs, int64_t npad) {
+                          int64_t nrhs, int64_t npad, int cs) {
   using C = typename Cx<T>::type;
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (t >= P * r * npad) return;
@@ -69,7 +71,7 @@ __global__ void k_leaf_in(const typename Cx<T>::type *__restrict__ W,
       acc.y += c.y;
     }
   }
-  y[act_off(j, a, n, P, r)] = acc;
+  y[act_off(j, a, n, P, r, cs)] = acc;
 }
 
 // u[(i n0 + p) ld + n] = sum_a W[i][p][a] z[i][a][n]
@@ -77,7 +79,7 @@ template <class T>
 __global__ void k_leaf_out(const typename Cx<T>::type *__restrict__ W,
                            const typename Cx<T>::type *__restrict__ z,
                            typename Cx<T>::type *__restrict__ u, int64_t ld, int64_t P, int n0,
-                           int r, int64_t nrhs) {
+                           int r, int64_t nrhs, int cs) {
   using C = typename Cx<T>::type;
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (t >= P * n0 * nrhs) return;
@@ -87,7 +89,7 @@ __global__ void k_leaf_out(const typename Cx<T>::type *__restrict__ W,
   const C *w = W + (i * n0 + p) * r;
   C acc{0, 0};
   for (int a = 0; a < r; ++a) {
-    const C c = cmul(w[a], z[act_off(i, a, n, P, r)]);
+    const C c = cmul(w[a], z[act_off(i, a, n, P, r, cs)]);
     acc.x += c.x;
     acc.y += c.y;
   }
@@ -105,7 +107,8 @@ template <class T>
 __global__ void k_butterfly(const typename Cx<T>::type *__restrict__ Fb,
                             const typename Cx<T>::type *__restrict__ x,
                             typename Cx<T>::type *__restrict__ y, int64_t nb, int64_t blo, int R,
-                            int r, int strided_in, int tconj, int64_t nslots, int64_t npad) {
+                            int r, int strided_in, int tconj, int64_t nslots, int64_t npad,
+                            int cs) {
   using C = typename Cx<T>::type;
   const int Rr = R * r;
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -121,21 +124,21 @@ __global__ void k_butterfly(const typename Cx<T>::type *__restrict__ Fb,
     if (tconj) {
       const C *blk = Fb + ((R * hi + ci) * blo + lo) * r * Rr;
       for (int k = 0; k < r; ++k) {
-        const C c = cmulc(x[act_off(s_in, k, n, nslots, r)], blk[k * Rr + co * r + a]);
+        const C c = cmulc(x[act_off(s_in, k, n, nslots, r, cs)], blk[k * Rr + co * r + a]);
         acc.x += c.x;
         acc.y += c.y;
       }
     } else {
       const C *row = Fb + (((R * hi + co) * blo + lo) * r + a) * Rr + ci * r;
       for (int k = 0; k < r; ++k) {
-        const C c = cmul(row[k], x[act_off(s_in, k, n, nslots, r)]);
+        const C c = cmul(row[k], x[act_off(s_in, k, n, nslots, r, cs)]);
         acc.x += c.x;
         acc.y += c.y;
       }
     }
   }
   const int64_t s_out = slot_of(b, co, blo, R, strided_in == 0);
-  y[act_off(s_out, a, n, nslots, r)] = acc;
+  y[act_off(s_out, a, n, nslots, r, cs)] = acc;
 }
 
 // y[(a m + b)][k] = S[a][b][k] x[(b m + a)][k]  (forward, M^h)
@@ -143,7 +146,7 @@ __global__ void k_butterfly(const typename Cx<T>::type *__restrict__ Fb,
 template <class T>
 __global__ void k_middle(const T *__restrict__ S, const typename Cx<T>::type *__restrict__ x,
                          typename Cx<T>::type *__restrict__ y, int64_t m, int r, int transpose,
-                         int64_t npad) {
+                         int64_t npad, int cs) {
   using C = typename Cx<T>::type;
   const int64_t nslots = m * m;
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -153,8 +156,8 @@ __global__ void k_middle(const T *__restrict__ S, const typename Cx<T>::type *__
   const int64_t so = t / (npad * r);
   const int64_t a = so / m, b = so - a * m;
   const T s = S[(transpose ? b * m + a : so) * r + k];
-  const C v = x[act_off(b * m + a, k, n, nslots, r)];
-  y[act_off(so, k, n, nslots, r)] = C{s * v.x, s * v.y};
+  const C v = x[act_off(b * m + a, k, n, nslots, r, cs)];
+  y[act_off(so, k, n, nslots, r, cs)] = C{s * v.x, s * v.y};
 }
 
 // grad[R hi + cx][lo][rx][cy r + ry] = sum_n X[strided(b,cx)][rx][n] conj(Y[contig(b,cy)][ry][n])
@@ -162,7 +165,7 @@ template <class T>
 __global__ void k_level_grad(const typename Cx<T>::type *__restrict__ X,
                              const typename Cx<T>::type *__restrict__ Y,
                              typename Cx<T>::type *__restrict__ grad, int64_t nb, int64_t blo,
-                             int R, int r, int64_t nslots, int64_t nrhs) {
+                             int R, int r, int64_t nslots, int64_t nrhs, int cs) {
   using C = typename Cx<T>::type;
   const int Rr = R * r;
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -176,7 +179,7 @@ __global__ void k_level_grad(const typename Cx<T>::type *__restrict__ X,
   const int64_t sy = slot_of(b, cy, blo, R, false);
   C acc{0, 0};
   for (int64_t n = 0; n < nrhs; ++n) {
-    const C c = cmulc(X[act_off(sx, rx, n, nslots, r)], Y[act_off(sy, ry, n, nslots, r)]);
+    const C c = cmulc(X[act_off(sx, rx, n, nslots, r, cs)], Y[act_off(sy, ry, n, nslots, r, cs)]);
     acc.x += c.x;
     acc.y += c.y;
   }
@@ -190,7 +193,7 @@ template <class T>
 __global__ void k_leaf_grad(const typename Cx<T>::type *__restrict__ user, int64_t ld,
                             const typename Cx<T>::type *__restrict__ act,
                             typename Cx<T>::type *__restrict__ grad, int64_t P, int n0, int r,
-                            int64_t nrhs) {
+                            int64_t nrhs, int cs) {
   using C = typename Cx<T>::type;
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (t >= P * n0 * r) return;
@@ -199,7 +202,7 @@ __global__ void k_leaf_grad(const typename Cx<T>::type *__restrict__ user, int64
   const int64_t j = t / (r * n0);
   C acc{0, 0};
   for (int64_t n = 0; n < nrhs; ++n) {
-    const C c = cmulc(user[(j * n0 + p) * ld + n], act[act_off(j, a, n, P, r)]);
+    const C c = cmulc(user[(j * n0 + p) * ld + n], act[act_off(j, a, n, P, r, cs)]);
     acc.x += c.x;
     acc.y += c.y;
   }
@@ -210,7 +213,7 @@ __global__ void k_leaf_grad(const typename Cx<T>::type *__restrict__ user, int64
 template <class T>
 __global__ void k_middle_grad(const typename Cx<T>::type *__restrict__ dz,
                               const typename Cx<T>::type *__restrict__ y, T *__restrict__ grad,
-                              int64_t m, int r, int64_t nrhs) {
+                              int64_t m, int r, int64_t nrhs, int cs) {
   const int64_t nslots = m * m;
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (t >= nslots * r) return;
@@ -219,8 +222,8 @@ __global__ void k_middle_grad(const typename Cx<T>::type *__restrict__ dz,
   const int64_t i = s / m, j = s - i * m;
   T acc = 0;
   for (int64_t n = 0; n < nrhs; ++n) {
-    const auto a = dz[act_off(s, k, n, nslots, r)];
-    const auto b = y[act_off(j * m + i, k, n, nslots, r)];
+    const auto a = dz[act_off(s, k, n, nslots, r, cs)];
+    const auto b = y[act_off(j * m + i, k, n, nslots, r, cs)];
     acc += a.x * b.x + a.y * b.y;
   }
   grad[t] = acc;
@@ -232,30 +235,30 @@ template <class T>
 hipError_t level_op_t(const bf_plan *p, const LevelOp &op, const void *in, int64_t ld_in,
                       void *out, int64_t ld_out, int64_t nrhs, hipStream_t s) {
   using C = typename Cx<T>::type;
-  const int64_t nchunks = (nrhs + kChunk - 1) / kChunk;
-  const int64_t npad = nchunks * kChunk;
+  const int cs = p->cs;
+  const int64_t npad = ((nrhs + (1 << cs) - 1) >> cs) << cs;
   const int bs = 256;
   switch (op.kind) {
     case LevelOp::kLeafIn:
       hipLaunchKernelGGL(k_leaf_in<T>, dim3(blocks_for(p->P * p->r * npad, bs)), dim3(bs), 0, s,
                          (const C *)op.mat, (const C *)in, ld_in, (C *)out, p->P, p->n0, p->r,
-                         nrhs, npad);
+                         nrhs, npad, cs);
       break;
     case LevelOp::kButterfly:
       hipLaunchKernelGGL(k_butterfly<T>, dim3(blocks_for(op.nb * p->R * p->r * npad, bs)),
                          dim3(bs), 0, s, (const C *)op.mat, (const C *)in, (C *)out, op.nb,
                          op.blo, p->R, p->r, op.mode == kStridedIn ? 1 : 0, op.tconj ? 1 : 0,
-                         p->P, npad);
+                         p->P, npad, cs);
       break;
     case LevelOp::kMiddle:
       hipLaunchKernelGGL(k_middle<T>, dim3(blocks_for(p->m * p->m * p->r * npad, bs)), dim3(bs),
                          0, s, (const T *)op.mat, (const C *)in, (C *)out, p->m, p->r,
-                         op.tconj ? 1 : 0, npad);
+                         op.tconj ? 1 : 0, npad, cs);
       break;
     case LevelOp::kLeafOut:
       hipLaunchKernelGGL(k_leaf_out<T>, dim3(blocks_for(p->P * p->n0 * nrhs, bs)), dim3(bs), 0,
                          s, (const C *)op.mat, (const C *)in, (C *)out, ld_out, p->P, p->n0,
-                         p->r, nrhs);
+                         p->r, nrhs, cs);
       break;
   }
   return hipGetLastError();
@@ -276,11 +279,11 @@ hipError_t launch_level_grad(const bf_plan *p, const LevelOp &op, const void *X,
   if (p->prec == BF_PREC_F64)
     hipLaunchKernelGGL(k_level_grad<double>, dim3(blocks_for(total, bs)), dim3(bs), 0, s,
                        (const double2 *)X, (const double2 *)Y, (double2 *)grad, op.nb, op.blo,
-                       p->R, p->r, p->P, nrhs);
+                       p->R, p->r, p->P, nrhs, p->cs);
   else
     hipLaunchKernelGGL(k_level_grad<float>, dim3(blocks_for(total, bs)), dim3(bs), 0, s,
                        (const float2 *)X, (const float2 *)Y, (float2 *)grad, op.nb, op.blo, p->R,
-                       p->r, p->P, nrhs);
+                       p->r, p->P, nrhs, p->cs);
   return hipGetLastError();
 }
 
@@ -291,11 +294,11 @@ hipError_t launch_leaf_grad(const bf_plan *p, const void *user, int64_t ld, cons
   if (p->prec == BF_PREC_F64)
     hipLaunchKernelGGL(k_leaf_grad<double>, dim3(blocks_for(total, bs)), dim3(bs), 0, s,
                        (const double2 *)user, ld, (const double2 *)act, (double2 *)grad, p->P,
-                       p->n0, p->r, nrhs);
+                       p->n0, p->r, nrhs, p->cs);
   else
     hipLaunchKernelGGL(k_leaf_grad<float>, dim3(blocks_for(total, bs)), dim3(bs), 0, s,
                        (const float2 *)user, ld, (const float2 *)act, (float2 *)grad, p->P,
-                       p->n0, p->r, nrhs);
+                       p->n0, p->r, nrhs, p->cs);
   return hipGetLastError();
 }
 
@@ -305,10 +308,12 @@ hipError_t launch_middle_grad(const bf_plan *p, const void *dz, const void *y, v
   const int64_t total = p->m * p->m * p->r;
   if (p->prec == BF_PREC_F64)
     hipLaunchKernelGGL(k_middle_grad<double>, dim3(blocks_for(total, bs)), dim3(bs), 0, s,
-                       (const double2 *)dz, (const double2 *)y, (double *)grad, p->m, p->r, nrhs);
+                       (const double2 *)dz, (const double2 *)y, (double *)grad, p->m, p->r, nrhs,
+                       p->cs);
   else
     hipLaunchKernelGGL(k_middle_grad<float>, dim3(blocks_for(total, bs)), dim3(bs), 0, s,
-                       (const float2 *)dz, (const float2 *)y, (float *)grad, p->m, p->r, nrhs);
+                       (const float2 *)dz, (const float2 *)y, (float *)grad, p->m, p->r, nrhs,
+                       p->cs);
   return hipGetLastError();
 }
 

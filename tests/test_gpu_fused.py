@@ -33,19 +33,22 @@ def fio4096():
     return oracle.construct_factors(kernels.fio(4096), leaf=16, r=16, method="sampling", seed=0)
 
 
-def _handle(f, prec, kmax=None):
+def _handle(f, prec, kmax=None, cols=None):
+    """Handle on the fused path; kmax / cols pick the pass depth and wave geometry."""
     from paper_1502_01379_amd import BFHandle
-    old = os.environ.get("BF_FUSED_KMAX")
-    if kmax is not None:
-        os.environ["BF_FUSED_KMAX"] = str(kmax)
+    env = {"BF_FUSED_KMAX": kmax, "BF_FUSED_COLS": cols}
+    old = {k: os.environ.get(k) for k in env}
+    for k, v in env.items():
+        if v is not None:
+            os.environ[k] = str(v)
     try:
         h = BFHandle(f, prec)
     finally:
-        if kmax is not None:
-            if old is None:
-                del os.environ["BF_FUSED_KMAX"]
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
             else:
-                os.environ["BF_FUSED_KMAX"] = old
+                os.environ[k] = v
     assert h.path == 1, "expected the fused MFMA path"
     return h
 
@@ -54,28 +57,29 @@ def _dev(x, dev):
     return torch.as_tensor(x).to(dev, torch.complex64)
 
 
+@pytest.mark.parametrize("cols", [16, 32])
 @pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("nrhs,pad", [(64, 0), (1, 0), (33, 3), (130, 2)])
-def test_fused_apply_and_adjoint(dev, fio4096, prec, nrhs, pad):
+def test_fused_apply_and_adjoint(dev, fio4096, prec, nrhs, pad, cols):
     f = fio4096
     N = 4096
     g = complex_gaussian((N, nrhs), 100 + nrhs)
     gl = np.zeros((N, nrhs + pad), dtype=complex)
     gl[:, :nrhs] = g
     gd = _dev(gl, dev)[:, :nrhs]
-    h = _handle(f, prec)
+    h = _handle(f, prec, cols=cols)
     u = h.apply(gd).cpu().numpy()
     assert oracle.rel_err(u, oracle.bf_apply(f, g)) < TOL[prec]
     v = h.apply_adjoint(gd).cpu().numpy()
     assert oracle.rel_err(v, oracle.bf_apply_adjoint(f, g)) < TOL[prec]
 
 
-@pytest.mark.parametrize("kmax", [1, 2, 3, 4])
-def test_fused_pass_depths_agree(dev, fio4096, kmax):
+@pytest.mark.parametrize("cols,kmax", [(16, 1), (16, 2), (16, 3), (16, 4), (32, 1), (32, 2), (32, 3)])
+def test_fused_pass_depths_agree(dev, fio4096, cols, kmax):
     # the same factor product split into passes of 1 to 4 levels
     g = complex_gaussian((4096, 40), 5)
     ref = oracle.bf_apply(fio4096, g)
-    h = _handle(fio4096, "f32", kmax=kmax)
+    h = _handle(fio4096, "f32", kmax=kmax, cols=cols)
     u = h.apply(_dev(g, dev)).cpu().numpy()
     assert oracle.rel_err(u, ref) < TOL["f32"]
 
@@ -87,7 +91,7 @@ def test_fused_tree_depths(dev, L):
     N = 16 * 2 ** L
     g = complex_gaussian((N, 35), L)
     for prec in PRECS:
-        h = _handle(f, prec)
+        h = _handle(f, prec, cols=16 if L % 4 else 32)
         u = h.apply(_dev(g, dev)).cpu().numpy()
         assert oracle.rel_err(u, oracle.bf_apply(f, g)) < TOL[prec], prec
         v = h.apply_adjoint(_dev(g, dev)).cpu().numpy()
@@ -127,12 +131,12 @@ def test_full_size_2_20_256_rhs(dev):
     gd = torch.from_numpy(g).to(dev)
     cols = [0, 131, 255]
     ref = oracle.bf_apply(f, g[:, cols].astype(np.complex128))
-    for prec in ["f32", "bf16x3"]:
-        h = _handle(f, prec)
+    for prec, wcols in [("f32", 16), ("bf16x3", 16), ("bf16x3", 32)]:
+        h = _handle(f, prec, cols=wcols)
         u = h.apply(gd)
         torch.cuda.synchronize()
         err = oracle.rel_err(u[:, cols].cpu().numpy(), ref)
-        print(f"N=2^20 {prec} rel err {err:.3e}", flush=True)
+        print(f"N=2^20 {prec} wave columns {wcols} rel err {err:.3e}", flush=True)
         assert err < TOL[prec]
         h.close()
         del u
