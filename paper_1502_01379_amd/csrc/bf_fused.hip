@@ -361,7 +361,7 @@ bf_status fused_build(bf_plan *p, const bf_factors_host *f) {
   const int kcap = cols == 32 ? 3 : 4;
   // FP32 passes are MFMA-bound and keep their best MFMA utilisation at three
   // levels; split-precision passes are HBM-bound and gain from four (fewer passes)
-  int kmax = std::min(kcap, prec == kF32 ? 3 : 4);
+  int kmax = std::min(kcap, p->prec == BF_PREC_F32 ? 3 : 4);
   if (const char *e = std::getenv("BF_FUSED_KMAX")) kmax = std::max(1, std::min(kcap, std::atoi(e)));
   p->cs = cols == 32 ? 5 : 4;
   const int prec = p->prec == BF_PREC_F32 ? kF32 : p->prec == BF_PREC_SPLIT_BF16 ? kBF16 : kF16;
