@@ -44,7 +44,42 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 1 GiB device copy (reference for HBM byte counters)")
+    ap.add_argument("--backward", action="store_true",
+                    help="time bf_backward (gradients for every factor block and g) instead")
     return ap.parse_args()
+
+
+def bench_backward(args):
+    """bf_backward on the differentiation workload: N = 2^log2n, r = 16, nrhs columns."""
+    import torch
+    from bf_inputs import complex_gaussian, synthetic_factors
+    from paper_1502_01379_amd import BFHandle, BF_BWD_RECOMPUTE
+    dev = torch.device("cuda:0")
+    L = args.log2n - 4
+    N = 16 * 2 ** L
+    f = synthetic_factors(2, 16, L, 16, seed=30)
+    g = torch.from_numpy(complex_gaussian((N, args.nrhs), 31, dtype=np.complex64)).to(dev)
+    gu = torch.from_numpy(complex_gaussian((N, args.nrhs), 32, dtype=np.complex64)).to(dev)
+    h = BFHandle(f, args.precision)
+    for _ in range(args.warmup):
+        h.backward(g, gu, flags=BF_BWD_RECOMPUTE)
+    torch.cuda.synchronize()
+    h.set_profiling(True)
+    h.kernel_times(reset=True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        h.backward(g, gu, flags=BF_BWD_RECOMPUTE)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    kt = h.kernel_times(reset=True)
+    top = sorted(kt.items(), key=lambda kv: -kv[1][0])[:8]
+    out = {"metric": "bf_backward ms (grad of every factor block and of g)", "value": ms,
+           "unit": "ms", "higher_is_better": False, "precision": args.precision,
+           "config": {"N": N, "L": L, "r": 16, "nrhs": args.nrhs},
+           "top_kernels_ms_per_call": {k: v[0] / args.steps for k, v in top}}
+    print(json.dumps(out), flush=True)
 
 
 def pass_work(name, L, r, leaf, nrhs, K, has_leaf, has_middle):
@@ -74,6 +109,9 @@ def main():
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the library has no "
               "multi-GPU path. Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
+    if args.backward:
+        bench_backward(args)
+        return
     import torch
 
     from bf_inputs import complex_gaussian, synthetic_factors

@@ -150,6 +150,7 @@ void build_ops(bf_plan *p, const Canon &c) {
     op.blo = ipow(R, L - l - 1);
     op.tconj = tconj;
     op.mat = arr;
+    op.level = l;
     op.name = std::string(nm) + std::to_string(l);
     return op;
   };
@@ -243,6 +244,8 @@ bf_status run_ops(bf_plan *p, const std::vector<LevelOp> &ops, const void *g, vo
 bf_plan::~bf_plan() {
   for (auto *fp : fwd_passes) bfly::fused_free(fp);
   for (auto *fp : adj_passes) bfly::fused_free(fp);
+  for (auto *fp : bwd_fwd) bfly::fused_free(fp);
+  for (auto *fp : bwd_adj) bfly::fused_free(fp);
   for (void *d : allocs) (void)hipFree(d);
   if (ws) (void)hipFree(ws);
   for (auto &r : prof_pending) {
@@ -435,6 +438,24 @@ bf_status bf_backward(bf_handle p, const void *g, const void *grad_u, void *grad
   const auto &F = p->fwd_ops;   // F[0] leaf_in, F[1..2h+1], F[2h+2] leaf_out
   const auto &A = p->adj_ops;   // A[0] leaf_in(U^*), A[k] adjoint of F[2h+2-k]
   hipError_t e;
+  // on the fused path every butterfly level runs as a one-level FP32 MFMA pass and
+  // the block gradients as MFMA contractions; other ops use the per-level kernels
+  if (p->path == 1 && !p->bwd_ready && p->cs == 4) {
+    if ((st = bfly::fused_build_backward(p, s)) != BF_OK) return st;
+  }
+  const bool fast = p->bwd_ready;
+  auto run_op = [&](bool adj, int t, const void *in, void *out) -> hipError_t {
+    const LevelOp &op = adj ? A[t] : F[t];
+    const bfly::FusedPass *fp = fast ? (adj ? p->bwd_adj[t] : p->bwd_fwd[t]) : nullptr;
+    if (fp) return bfly::fused_run_level(p, fp, in, out, nrhs, s);
+    if (fast && (op.kind == LevelOp::kLeafIn || op.kind == LevelOp::kLeafOut))
+      return bfly::launch_leaf16(p, op, in, out, nrhs, ld, s);
+    return bfly::launch_level_op(p, op, in, ld, out, ld, nrhs, s);
+  };
+  auto run_grad = [&](const LevelOp &op, const void *X, const void *Y, void *dst) -> hipError_t {
+    if (fast) return bfly::launch_grad_level_mfma(p, op, X, Y, dst, nrhs, s);
+    return bfly::launch_level_grad(p, op, X, Y, dst, nrhs, s);
+  };
 #define BWD_LAUNCH(name, call)                                                         \
   do {                                                                                 \
     bfly::prof_begin(p, name, s);                                                      \
@@ -449,7 +470,7 @@ bf_status bf_backward(bf_handle p, const void *g, const void *grad_u, void *grad
     char *scratch[2] = {seg0, nseg >= 2 ? seg0 + ab : dbuf[0]};
     for (int t = 0; t < nact; ++t) {
       char *dst = (t % kc == 0) ? ckpt(t) : scratch[t & 1];
-      BWD_LAUNCH(F[t].name.c_str(), bfly::launch_level_op(p, F[t], cur, ld, dst, ld, nrhs, s));
+      BWD_LAUNCH(F[t].name.c_str(), run_op(false, t, cur, dst));
       cur = dst;
     }
   }
@@ -465,7 +486,7 @@ bf_status bf_backward(bf_handle p, const void *g, const void *grad_u, void *grad
     for (int q = base + 1; q < std::min(base + kc, nact); ++q) {
       char *dst = seg0 + (size_t)((q % kc) - 1) * ab;
       bfly::prof_begin(p, F[q].name + "_recompute", s);
-      hipError_t e2 = bfly::launch_level_op(p, F[q], cur, ld, dst, ld, nrhs, s);
+      hipError_t e2 = run_op(false, q, cur, dst);
       bfly::prof_end(p, s);
       if (e2 != hipSuccess) return e2;
       cur = dst;
@@ -477,9 +498,13 @@ bf_status bf_backward(bf_handle p, const void *g, const void *grad_u, void *grad
   const int T = nact - 1;  // index of a_{2h+1}
   // U^L: grad_UL = sum delta_u a_T^*, delta_T = (U^L)^* delta_u
   if ((e = ensure_seg(T)) != hipSuccess) return fail(p, BF_ERR_HIP, std::string("recompute: ") + hipGetErrorString(e));
-  if (grads && grads->UL) BWD_LAUNCH("grad_UL", bfly::launch_leaf_grad(p, grad_u, ld, act(T), grads->UL, nrhs, s));
+  auto leaf_grad = [&](const void *user, const void *a, void *dst) -> hipError_t {
+    if (fast) return bfly::launch_grad_leaf_mfma(p, user, ld, a, dst, nrhs, s);
+    return bfly::launch_leaf_grad(p, user, ld, a, dst, nrhs, s);
+  };
+  if (grads && grads->UL) BWD_LAUNCH("grad_UL", leaf_grad(grad_u, act(T), grads->UL));
   int cur_d = 0;
-  BWD_LAUNCH(A[0].name.c_str(), bfly::launch_level_op(p, A[0], grad_u, ld, dbuf[cur_d], ld, nrhs, s));
+  BWD_LAUNCH(A[0].name.c_str(), run_op(true, 0, grad_u, dbuf[cur_d]));
   for (int t = T; t >= 1; --t) {
     if ((e = ensure_seg(t - 1)) != hipSuccess) return fail(p, BF_ERR_HIP, std::string("recompute: ") + hipGetErrorString(e));
     const LevelOp &op = F[t];
@@ -497,18 +522,18 @@ bf_status bf_backward(bf_handle p, const void *g, const void *grad_u, void *grad
       }
       if (dst) {
         if (is_g)
-          BWD_LAUNCH("grad_G", bfly::launch_level_grad(p, op, dout, xin, dst, nrhs, s));
+          BWD_LAUNCH("grad_G", run_grad(op, dout, xin, dst));
         else
-          BWD_LAUNCH("grad_H", bfly::launch_level_grad(p, op, xin, dout, dst, nrhs, s));
+          BWD_LAUNCH("grad_H", run_grad(op, xin, dout, dst));
       }
     }
     const LevelOp &aop = A[nact - t];
-    BWD_LAUNCH(aop.name.c_str(), bfly::launch_level_op(p, aop, dout, ld, dbuf[cur_d ^ 1], ld, nrhs, s));
+    BWD_LAUNCH(aop.name.c_str(), run_op(true, nact - t, dout, dbuf[cur_d ^ 1]));
     cur_d ^= 1;
   }
   // V^L: grad_VL = sum g delta_0^*, grad_g = V^L delta_0
-  if (grads && grads->VL) BWD_LAUNCH("grad_VL", bfly::launch_leaf_grad(p, g, ld, dbuf[cur_d], grads->VL, nrhs, s));
-  if (grad_g) BWD_LAUNCH(A[nact].name.c_str(), bfly::launch_level_op(p, A[nact], dbuf[cur_d], ld, grad_g, ld, nrhs, s));
+  if (grads && grads->VL) BWD_LAUNCH("grad_VL", leaf_grad(g, dbuf[cur_d], grads->VL));
+  if (grad_g) BWD_LAUNCH(A[nact].name.c_str(), run_op(true, nact, dbuf[cur_d], grad_g));
 #undef BWD_LAUNCH
   return BF_OK;
 }

@@ -1,0 +1,283 @@
+// Backward-pass kernels for handles on the fused path (radix 2, leaf 16, r 16).
+//
+//  * k_pack_level: packs one butterfly level of the canonical factors (device,
+//    complex64) into the per-lane A-operand order of the 16-column FP32 block
+//    product (one block per butterfly, the order a one-level fused pass reads),
+//    so the backward pass can run every level through the fused kernel.
+//  * k_grad_level: the gradient of every block of one level,
+//        grad[2 hi + cx][lo][rx][cy r + ry] = sum_n X[strided(b,cx)][rx][n] conj(Y[contig(b,cy)][ry][n]),
+//    (grad_B = sum_n d_out x_in^* for G levels with X = d_out, Y = x_in;
+//     grad_W = sum_n x_in d_out^* for H levels with X = x_in, Y = d_out),
+//    as a 32 x 32 x (2 nrhs) real contraction on the matrix cores.  One
+//    wavefront per butterfly, columns in chunks of 16 staged through LDS
+//    (transposed, padded rows: conflict-free reads), fixed summation order.
+#include <hip/hip_runtime.h>
+
+#include "bf_internal.h"
+
+namespace bfly {
+namespace {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
+constexpr int kR = 16;  // rank == leaf size on this path
+
+// value = [Re M, -Im M][o][(part, k)] for the block of butterfly b, with
+//   direct: M[o][k] = Fb[2 hi + o / r][lo][o % r][k]
+//   tconj:  M[o][k] = conj(Fb[2 hi + k / r][lo][k % r][o])
+__device__ __forceinline__ float block_value(const float2 *__restrict__ Fb, int64_t hi, int64_t lo,
+                                             int64_t blo, int tconj, int o, int k, int part) {
+  float2 v;
+  if (tconj)
+    v = Fb[(((2 * hi + k / kR) * blo + lo) * kR + (k % kR)) * (2 * kR) + o];
+  else
+    v = Fb[(((2 * hi + o / kR) * blo + lo) * kR + (o % kR)) * (2 * kR) + k];
+  if (tconj) v.y = -v.y;
+  return part == 0 ? v.x : -v.y;
+}
+
+// one thread per (butterfly, lane, float f of the lane's 32): block layout of
+// the 16-column FP32 product: f = 16 T + s, s = 8 part + 4 c' + rho; lane (i, e)
+// with i = lane % 16, e = lane / 16; output row 16 T + i, input row 16 c' + 4 e + rho
+__global__ void k_pack_level(const float2 *__restrict__ Fb, float *__restrict__ out, int64_t nb,
+                             int64_t blo, int tconj) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= nb * 64 * 32) return;
+  const int f = (int)(t & 31);
+  const int lane = (int)((t >> 5) & 63);
+  const int64_t b = t >> 11;
+  const int64_t hi = b / blo, lo = b - hi * blo;
+  const int T = f >> 4, s = f & 15;
+  const int part = s >> 3, cp = (s >> 2) & 1, rho = s & 3;
+  const int i = lane & 15, e = lane >> 4;
+  const float v = block_value(Fb, hi, lo, blo, tconj, 16 * T + i, 16 * cp + 4 * e + rho, part);
+  out[b * 2048 + ((f >> 2) * 64 + lane) * 4 + (f & 3)] = v;
+}
+
+constexpr int kRowPad = 272;  // bytes per column of a staged 32-row chunk (256 + 16)
+
+// Stage rows (2 slots x 16 rows) x 16 columns [n0, n0 + 16) of one activation
+// operand into LDS as [column][row] complex, row stride kRowPad bytes.
+__device__ __forceinline__ void stage_chunk(const float2 *__restrict__ act, int64_t nslots,
+                                            int64_t s0, int64_t s1, int64_t n0, int cs,
+                                            char *lds, int lane) {
+  const int C = 1 << cs;
+  const int64_t chunk = n0 >> cs;
+  const int nb = (int)(n0 & (C - 1));
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int piece = v * 64 + lane;          // 256 pieces of 16 bytes (2 complex)
+    const int c = piece >> 7;                 // slot 0 or 1
+    const int p = (piece >> 4) & 7;           // row pair
+    const int n = piece & 15;                 // column within the 16
+    const int64_t slot = c ? s1 : s0;
+    const f32x4 *src = reinterpret_cast<const f32x4 *>(
+        act + ((chunk * nslots + slot) * 8 + p) * (2 * C) + (int64_t)(nb + n) * 2);
+    const f32x4 val = *src;
+    *reinterpret_cast<f32x4 *>(lds + n * kRowPad + (c * 16 + 2 * p) * 8) = val;
+  }
+}
+
+// Stage rows (2 leaves x 16 points) x 16 columns [n0, n0 + 16) of a user vector
+// [N][ld] into LDS as [column][row] complex, row stride kRowPad bytes; columns
+// at or past nrhs are zero.
+__device__ __forceinline__ void stage_user(const float2 *__restrict__ u, int64_t ld, int64_t row0,
+                                           int64_t n0, int64_t nrhs, char *lds, int lane) {
+#pragma unroll
+  for (int v = 0; v < 8; ++v) {
+    const int piece = v * 64 + lane;  // 512 complex: row = piece / 16, column = piece % 16
+    const int row = piece >> 4, n = piece & 15;
+    float2 val = make_float2(0.f, 0.f);
+    if (n0 + n < nrhs) val = u[(row0 + row) * ld + n0 + n];
+    *reinterpret_cast<float2 *>(lds + n * kRowPad + row * 8) = val;
+  }
+}
+
+// Gradient of two leaf blocks (leaves 2 pr, 2 pr + 1):
+//   grad[j][p][a] = sum_n U[(j n0 + p) ld + n] conj(act[j][a][n])
+// (grad U^L with U = delta_u, act = z^L; grad V^L with U = g, act = delta y^L).
+__global__ __launch_bounds__(256) void k_grad_leaf(const float2 *__restrict__ U, int64_t ld,
+                                                    const float2 *__restrict__ act,
+                                                    float2 *__restrict__ grad, int64_t npairs,
+                                                    int64_t nslots, int64_t nrhs, int cs) {
+  __shared__ __attribute__((aligned(16))) char lds[4][2][16 * kRowPad];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t pr = (int64_t)blockIdx.x * 4 + wave;
+  if (pr >= npairs) return;
+  char *lx = lds[wave][0], *ly = lds[wave][1];
+  const int i = lane & 31, eta = lane >> 5;
+  floatx16 dre = {}, dim = {};
+  const int64_t npad = ((nrhs + 15) >> 4) << 4;
+  for (int64_t n0 = 0; n0 < npad; n0 += 16) {
+    stage_user(U, ld, 2 * pr * kR, n0, nrhs, lx, lane);
+    stage_chunk(act, nslots, 2 * pr, 2 * pr + 1, n0, cs, ly, lane);
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      const int n = 8 * eta + s;
+      const f32x2 xv = *reinterpret_cast<const f32x2 *>(lx + n * kRowPad + i * 8);
+      const f32x2 yv = *reinterpret_cast<const f32x2 *>(ly + n * kRowPad + i * 8);
+      dre = __builtin_amdgcn_mfma_f32_32x32x2f32(xv.x, yv.x, dre, 0, 0, 0);
+      dre = __builtin_amdgcn_mfma_f32_32x32x2f32(xv.y, yv.y, dre, 0, 0, 0);
+      dim = __builtin_amdgcn_mfma_f32_32x32x2f32(xv.y, yv.x, dim, 0, 0, 0);
+      dim = __builtin_amdgcn_mfma_f32_32x32x2f32(-xv.x, yv.y, dim, 0, 0, 0);
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+#pragma unroll
+  for (int reg = 0; reg < 16; ++reg) {
+    const int row = 8 * (reg >> 2) + 4 * eta + (reg & 3);
+    const int c = row >> 4;
+    if ((i >> 4) != c) continue;  // only the two diagonal 16 x 16 blocks
+    float2 v;
+    v.x = dre[reg];
+    v.y = dim[reg];
+    grad[((2 * pr + c) * kR + (row & 15)) * kR + (i & 15)] = v;
+  }
+}
+
+// y[j][a][n] = sum_p conj(W[j][p][a]) x[(j n0 + p) ld + n]: one thread per (leaf, column)
+__global__ void k_leaf_in16(const float2 *__restrict__ W, const float2 *__restrict__ x, int64_t ld,
+                            float2 *__restrict__ y, int64_t P, int64_t nrhs, int64_t npad, int cs) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= P * npad) return;
+  const int64_t n = t % npad, j = t / npad;
+  float2 v[kR];
+#pragma unroll
+  for (int p = 0; p < kR; ++p)
+    v[p] = n < nrhs ? x[(j * kR + p) * ld + n] : make_float2(0.f, 0.f);
+  const float2 *w = W + j * kR * kR;
+  const int C = 1 << cs;
+  float2 *dst = y + ((n >> cs) * P + j) * 8 * (2 * C) + (n & (C - 1)) * 2;
+#pragma unroll
+  for (int a = 0; a < kR; ++a) {
+    float re = 0.f, im = 0.f;
+#pragma unroll
+    for (int p = 0; p < kR; ++p) {
+      const float2 c = w[p * kR + a];
+      re += c.x * v[p].x + c.y * v[p].y;
+      im += c.x * v[p].y - c.y * v[p].x;
+    }
+    dst[(a >> 1) * (2 * C) + (a & 1)] = make_float2(re, im);
+  }
+}
+
+// u[(i n0 + p) ld + n] = sum_a W[i][p][a] z[i][a][n]: one thread per (leaf, column)
+__global__ void k_leaf_out16(const float2 *__restrict__ W, const float2 *__restrict__ z,
+                             float2 *__restrict__ u, int64_t ld, int64_t P, int64_t nrhs, int cs) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= P * nrhs) return;
+  const int64_t n = t % nrhs, i = t / nrhs;
+  const int C = 1 << cs;
+  const float2 *src = z + ((n >> cs) * P + i) * 8 * (2 * C) + (n & (C - 1)) * 2;
+  float2 v[kR];
+#pragma unroll
+  for (int a = 0; a < kR; ++a) v[a] = src[(a >> 1) * (2 * C) + (a & 1)];
+  const float2 *w = W + i * kR * kR;
+#pragma unroll
+  for (int p = 0; p < kR; ++p) {
+    float re = 0.f, im = 0.f;
+#pragma unroll
+    for (int a = 0; a < kR; ++a) {
+      const float2 c = w[p * kR + a];
+      re += c.x * v[a].x - c.y * v[a].y;
+      im += c.x * v[a].y + c.y * v[a].x;
+    }
+    u[(i * kR + p) * ld + n] = make_float2(re, im);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_grad_level(const float2 *__restrict__ X,
+                                                     const float2 *__restrict__ Y,
+                                                     float2 *__restrict__ grad, int64_t nb,
+                                                     int64_t blo, int64_t nslots, int64_t nrhs,
+                                                     int cs) {
+  __shared__ __attribute__((aligned(16))) char lds[4][2][16 * kRowPad];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t b = (int64_t)blockIdx.x * 4 + wave;
+  if (b >= nb) return;
+  const int64_t hi = b / blo, lo = b - hi * blo;
+  const int64_t sx0 = hi * 2 * blo + lo, sx1 = sx0 + blo;        // strided slots
+  const int64_t sy0 = hi * 2 * blo + 2 * lo, sy1 = sy0 + 1;      // contiguous slots
+  char *lx = lds[wave][0], *ly = lds[wave][1];
+  const int i = lane & 31, eta = lane >> 5;
+  floatx16 dre = {}, dim = {};
+  const int64_t npad = ((nrhs + 15) >> 4) << 4;
+  for (int64_t n0 = 0; n0 < npad; n0 += 16) {
+    stage_chunk(X, nslots, sx0, sx1, n0, cs, lx, lane);
+    stage_chunk(Y, nslots, sy0, sy1, n0, cs, ly, lane);
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      const int n = 8 * eta + s;
+      const f32x2 xv = *reinterpret_cast<const f32x2 *>(lx + n * kRowPad + i * 8);
+      const f32x2 yv = *reinterpret_cast<const f32x2 *>(ly + n * kRowPad + i * 8);
+      // columns past nrhs hold zeros in every activation buffer
+      dre = __builtin_amdgcn_mfma_f32_32x32x2f32(xv.x, yv.x, dre, 0, 0, 0);
+      dre = __builtin_amdgcn_mfma_f32_32x32x2f32(xv.y, yv.y, dre, 0, 0, 0);
+      dim = __builtin_amdgcn_mfma_f32_32x32x2f32(xv.y, yv.x, dim, 0, 0, 0);
+      dim = __builtin_amdgcn_mfma_f32_32x32x2f32(-xv.x, yv.y, dim, 0, 0, 0);
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  // lane (j, eta) holds D[8 q + 4 eta + v][j]: row (cx, rx), column j = cy r + ry
+#pragma unroll
+  for (int reg = 0; reg < 16; ++reg) {
+    const int row = 8 * (reg >> 2) + 4 * eta + (reg & 3);
+    const int cx = row >> 4, rx = row & 15;
+    float2 v;
+    v.x = dre[reg];
+    v.y = dim[reg];
+    grad[(((2 * hi + cx) * blo + lo) * kR + rx) * (2 * kR) + i] = v;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_grad_leaf_mfma(const bf_plan *p, const void *user, int64_t ld, const void *act,
+                                 void *grad, int64_t nrhs, hipStream_t s) {
+  const int64_t npairs = p->P / 2;
+  hipLaunchKernelGGL(k_grad_leaf, dim3((unsigned)((npairs + 3) / 4)), dim3(256), 0, s,
+                     (const float2 *)user, ld, (const float2 *)act, (float2 *)grad, npairs, p->P,
+                     nrhs, p->cs);
+  return hipGetLastError();
+}
+
+hipError_t launch_leaf16(const bf_plan *p, const LevelOp &op, const void *in, void *out,
+                         int64_t nrhs, int64_t ld, hipStream_t s) {
+  const int bs = 256;
+  const int cs = p->cs;
+  const int64_t npad = ((nrhs + (1 << cs) - 1) >> cs) << cs;
+  if (op.kind == LevelOp::kLeafIn)
+    hipLaunchKernelGGL(k_leaf_in16, dim3((unsigned)((p->P * npad + bs - 1) / bs)), dim3(bs), 0, s,
+                       (const float2 *)op.mat, (const float2 *)in, ld, (float2 *)out, p->P, nrhs,
+                       npad, cs);
+  else
+    hipLaunchKernelGGL(k_leaf_out16, dim3((unsigned)((p->P * nrhs + bs - 1) / bs)), dim3(bs), 0, s,
+                       (const float2 *)op.mat, (const float2 *)in, (float2 *)out, ld, p->P, nrhs,
+                       cs);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_level(const void *canon_level, void *out, int64_t nb, int64_t blo, bool tconj,
+                             hipStream_t s) {
+  const int bs = 256;
+  const int64_t total = nb * 64 * 32;
+  hipLaunchKernelGGL(k_pack_level, dim3((unsigned)((total + bs - 1) / bs)), dim3(bs), 0, s,
+                     (const float2 *)canon_level, (float *)out, nb, blo, tconj ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_level_mfma(const bf_plan *p, const LevelOp &op, const void *X, const void *Y,
+                                  void *grad, int64_t nrhs, hipStream_t s) {
+  hipLaunchKernelGGL(k_grad_level, dim3((unsigned)((op.nb + 3) / 4)), dim3(256), 0, s,
+                     (const float2 *)X, (const float2 *)Y, (float2 *)grad, op.nb, op.blo, p->P,
+                     nrhs, p->cs);
+  return hipGetLastError();
+}
+
+}  // namespace bfly

@@ -316,8 +316,8 @@ bf_status build_pass(bf_plan *p, const HostFactors &F, const PassPlan &pp, int p
   return st;
 }
 
-hipError_t launch_pass(const bf_plan *p, const FusedPass *fp, const void *in, void *out,
-                       int64_t nrhs, int64_t ld, hipStream_t s) {
+FusedArgs pass_args(const bf_plan *p, const FusedPass *fp, const void *in, void *out, int64_t nrhs,
+                    int64_t ld) {
   FusedArgs a;
   a.in = in;
   a.out = out;
@@ -339,6 +339,12 @@ hipError_t launch_pass(const bf_plan *p, const FusedPass *fp, const void *in, vo
   a.ngroups = 1;
   a.log_m = 0;
   while ((int64_t(1) << a.log_m) < a.m) ++a.log_m;
+  return a;
+}
+
+hipError_t launch_pass(const bf_plan *p, const FusedPass *fp, const void *in, void *out,
+                       int64_t nrhs, int64_t ld, hipStream_t s) {
+  FusedArgs a = pass_args(p, fp, in, out, nrhs, ld);
   const bool li = fp->in_kind == kInUser, lo = fp->out_kind == kOutUser;
   if (p->prec == BF_PREC_F32) return launch_prec<kF32>(a, fp->cols, fp->K, li, lo, s);
   if (p->prec == BF_PREC_SPLIT_BF16) return launch_prec<kBF16>(a, fp->cols, fp->K, li, lo, s);
@@ -427,6 +433,55 @@ hipError_t fused_run(bf_plan *p, bool adjoint, const void *g, void *u, int64_t n
     cur = dst;
   }
   return hipSuccess;
+}
+
+// One-level FP32 passes (16-column geometry) for every butterfly op of the
+// forward and adjoint op lists; their blocks are packed on the device from the
+// canonical factors the handle already holds.
+bf_status fused_build_backward(bf_plan *p, hipStream_t s) {
+  auto build = [&](const std::vector<LevelOp> &ops, std::vector<FusedPass *> &out) -> bf_status {
+    out.assign(ops.size(), nullptr);
+    for (size_t t = 0; t < ops.size(); ++t) {
+      const LevelOp &op = ops[t];
+      if (op.kind != LevelOp::kButterfly) continue;
+      FusedPass *fp = new FusedPass();
+      out[t] = fp;
+      fp->K = 1;
+      fp->cols = 16;
+      fp->log_slo = p->L - op.level - 1;
+      fp->mode_si = op.mode == kStridedIn ? 1 : 0;
+      fp->in_kind = kInAct;
+      fp->out_kind = kOutAct;
+      fp->ntiles = op.nb;
+      fp->name = op.name + "_pass";
+      void *d = nullptr;
+      const size_t bytes = (size_t)op.nb * kBlockBytes;
+      hipError_t e = hipMalloc(&d, bytes);
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        p->err = std::string("backward pack allocation: ") + hipGetErrorString(e);
+        return BF_ERR_ALLOC;
+      }
+      fp->owned.push_back(d);
+      fp->fac = d;
+      e = launch_pack_level(op.mat, d, op.nb, op.blo, op.tconj, s);
+      if (e != hipSuccess) {
+        p->err = std::string("backward pack: ") + hipGetErrorString(e);
+        return BF_ERR_HIP;
+      }
+    }
+    return BF_OK;
+  };
+  bf_status st = build(p->fwd_ops, p->bwd_fwd);
+  if (st == BF_OK) st = build(p->adj_ops, p->bwd_adj);
+  if (st == BF_OK) p->bwd_ready = true;
+  return st;
+}
+
+hipError_t fused_run_level(const bf_plan *p, const FusedPass *fp, const void *in, void *out,
+                           int64_t nrhs, hipStream_t s) {
+  FusedArgs a = pass_args(p, fp, in, out, nrhs, 0);
+  return launch_prec<kF32>(a, fp->cols, fp->K, false, false, s);
 }
 
 void fused_free(FusedPass *fp) {

@@ -40,6 +40,7 @@ struct LevelOp {
   int64_t blo = 0;   // see SlotMode
   bool tconj = false; // butterfly: conjugate-transposed blocks; middle: transposed S
   const void *mat = nullptr;  // canonical factor array of this op (device)
+  int level = -1;             // butterfly: tree level l of the factor
   std::string name;
 };
 
@@ -66,6 +67,10 @@ struct bf_plan {
   std::vector<bfly::LevelOp> fwd_ops, adj_ops;
   // fused path
   std::vector<bfly::FusedPass *> fwd_passes, adj_passes;
+  // one-level FP32 fused passes used by the backward pass, built on first use and
+  // indexed by the position of the op in fwd_ops / adj_ops (nullptr: not a butterfly)
+  std::vector<bfly::FusedPass *> bwd_fwd, bwd_adj;
+  bool bwd_ready = false;
   // middle weights, FP32 or FP64 by precision: S[i][j][k] and its transpose
   void *S = nullptr, *ST = nullptr;
 
@@ -96,8 +101,23 @@ hipError_t launch_leaf_grad(const bf_plan *p, const void *user, int64_t ld, cons
 hipError_t launch_middle_grad(const bf_plan *p, const void *dz, const void *y, void *grad,
                               int64_t nrhs, hipStream_t s);
 
+// Backward helpers for fused-path handles (bf_bwd.hip)
+hipError_t launch_pack_level(const void *canon_level, void *out, int64_t nb, int64_t blo, bool tconj,
+                             hipStream_t s);
+hipError_t launch_grad_level_mfma(const bf_plan *p, const LevelOp &op, const void *X, const void *Y,
+                                  void *grad, int64_t nrhs, hipStream_t s);
+hipError_t launch_grad_leaf_mfma(const bf_plan *p, const void *user, int64_t ld, const void *act,
+                                 void *grad, int64_t nrhs, hipStream_t s);
+// leaf-in / leaf-out ops for leaf 16, rank 16 in FP32, one thread per (leaf, column)
+hipError_t launch_leaf16(const bf_plan *p, const LevelOp &op, const void *in, void *out,
+                         int64_t nrhs, int64_t ld, hipStream_t s);
+
 // Fused path (bf_fused.hip)
 bool fused_supported(const bf_shape &sh, bf_precision prec);
+// one-level FP32 passes for the backward pass (blocks packed on the device)
+bf_status fused_build_backward(bf_plan *p, hipStream_t s);
+hipError_t fused_run_level(const bf_plan *p, const FusedPass *fp, const void *in, void *out,
+                           int64_t nrhs, hipStream_t s);
 bf_status fused_build(bf_plan *p, const bf_factors_host *f);
 hipError_t fused_run(bf_plan *p, bool adjoint, const void *g, void *u, int64_t nrhs, int64_t ld,
                      void *buf0, void *buf1, hipStream_t s);
