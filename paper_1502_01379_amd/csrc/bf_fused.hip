@@ -122,6 +122,7 @@ float pack_block(const cd *M, int prec, int cols, char *dst) {
 
 struct FusedPass {
   int K = 0, cols = 32, log_slo = 0, mode_si = 1, in_kind = kInAct, out_kind = kOutAct;
+  bool split = false;  // tile shared by a pair of wavefronts (k_fused_pass_x2)
   int64_t ntiles = 0;
   void *fac = nullptr, *leaf = nullptr;
   float *fscale = nullptr, *lscale = nullptr;
@@ -346,9 +347,10 @@ hipError_t launch_pass(const bf_plan *p, const FusedPass *fp, const void *in, vo
                        int64_t nrhs, int64_t ld, hipStream_t s) {
   FusedArgs a = pass_args(p, fp, in, out, nrhs, ld);
   const bool li = fp->in_kind == kInUser, lo = fp->out_kind == kOutUser;
-  if (p->prec == BF_PREC_F32) return launch_prec<kF32>(a, fp->cols, fp->K, li, lo, s);
-  if (p->prec == BF_PREC_SPLIT_BF16) return launch_prec<kBF16>(a, fp->cols, fp->K, li, lo, s);
-  return launch_prec<kF16>(a, fp->cols, fp->K, li, lo, s);
+  if (p->prec == BF_PREC_F32) return launch_prec<kF32>(a, fp->cols, fp->K, li, lo, fp->split, s);
+  if (p->prec == BF_PREC_SPLIT_BF16)
+    return launch_prec<kBF16>(a, fp->cols, fp->K, li, lo, fp->split, s);
+  return launch_prec<kF16>(a, fp->cols, fp->K, li, lo, fp->split, s);
 }
 
 }  // namespace
@@ -369,6 +371,10 @@ bf_status fused_build(bf_plan *p, const bf_factors_host *f) {
   // levels; split-precision passes are HBM-bound and gain from four (fewer passes)
   int kmax = std::min(kcap, p->prec == BF_PREC_F32 ? 3 : 4);
   if (const char *e = std::getenv("BF_FUSED_KMAX")) kmax = std::max(1, std::min(kcap, std::atoi(e)));
+  // passes of at least split_min levels (16-column geometry) share each tile
+  // between a pair of wavefronts
+  int split_min = 4;
+  if (const char *e = std::getenv("BF_FUSED_SPLIT")) split_min = std::atoi(e) <= 0 ? 99 : std::atoi(e);
   p->cs = cols == 32 ? 5 : 4;
   const int prec = p->prec == BF_PREC_F32 ? kF32 : p->prec == BF_PREC_SPLIT_BF16 ? kBF16 : kF16;
 
@@ -400,6 +406,7 @@ bf_status fused_build(bf_plan *p, const bf_factors_host *f) {
       FusedPass *fp = nullptr;
       st = build_pass(p, F, pp, prec, cols, nullptr, &fp);
       list.push_back(fp);
+      if (fp) fp->split = cols == 16 && fp->K >= 3 && fp->K >= split_min;
       if (st != BF_OK) return st;
       l_hi -= ks[t];
     }
@@ -412,6 +419,7 @@ bf_status fused_build(bf_plan *p, const bf_factors_host *f) {
       FusedPass *fp = nullptr;
       st = build_pass(p, F, pp, prec, cols, t == 0 ? (const float *)(adj ? dST : dS) : nullptr, &fp);
       list.push_back(fp);
+      if (fp) fp->split = cols == 16 && fp->K >= 3 && fp->K >= split_min;
       if (st != BF_OK) return st;
       l_lo += K;
     }
@@ -481,7 +489,7 @@ bf_status fused_build_backward(bf_plan *p, hipStream_t s) {
 hipError_t fused_run_level(const bf_plan *p, const FusedPass *fp, const void *in, void *out,
                            int64_t nrhs, hipStream_t s) {
   FusedArgs a = pass_args(p, fp, in, out, nrhs, 0);
-  return launch_prec<kF32>(a, fp->cols, fp->K, false, false, s);
+  return launch_prec<kF32>(a, fp->cols, fp->K, false, false, false, s);
 }
 
 void fused_free(FusedPass *fp) {

@@ -97,14 +97,21 @@ __device__ __forceinline__ BlockA load_block(const char *A, int lane) {
   return b;
 }
 
+// x * s = hi + lo with hi = RNE(x * s) and lo = RNE(x * s - hi), two values per
+// conversion (one packed convert yields both halves of a 32-bit register)
 template <class H8, class Hs>
 __device__ __forceinline__ void split8(const float *x, float s, H8 &hi, H8 &lo) {
+  typedef Hs h2 __attribute__((ext_vector_type(2)));
 #pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    const float v = x[j] * s;
-    const Hs h = (Hs)v;
-    hi[j] = h;
-    lo[j] = (Hs)(v - (float)h);
+  for (int j = 0; j < 8; j += 2) {
+    const f32x2 v = {x[j] * s, x[j + 1] * s};
+    const h2 h = __builtin_convertvector(v, h2);
+    const f32x2 r = v - __builtin_convertvector(h, f32x2);
+    const h2 l = __builtin_convertvector(r, h2);
+    hi[j] = h.x;
+    hi[j + 1] = h.y;
+    lo[j] = l.x;
+    lo[j + 1] = l.y;
   }
 }
 
@@ -396,7 +403,7 @@ void k_fused_pass(FusedArgs a) {
   constexpr int NB = NS / 2;
   constexpr int LOGC = COLS == 32 ? 5 : 4;
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform per wavefront
   const int n = lane & (COLS - 1), e = lane / COLS;
   int64_t tile, group;
   tile_of_block(a, tile, group);
@@ -571,6 +578,260 @@ void k_fused_pass(FusedArgs a) {
   });
 }
 
+// ---- split tiles: two wavefronts share one tile of one column chunk ----------------
+//
+// Wavefront h (0 or 1) of a pair holds the tile slots q = h 2^(K-1) + j,
+// j < 2^(K-1), so its state is half that of the pass above and four wavefronts
+// fit on a SIMD.  Levels 0 .. K-2 never pair slots of different halves (they
+// keep the top bit of q), so each wavefront runs them alone on its 2^(K-1)
+// slots, computing blocks h 2^(K-2) + beta'.  The last level pairs slot b with
+// slot 2^(K-1) + b: before it the pair swaps half of its slots through LDS
+// (wavefront 0 keeps the x0 operands of b < 2^(K-2), wavefront 1 the x1 operands
+// of b >= 2^(K-2)), and wavefront h' then computes the blocks b = h' 2^(K-2) + k,
+// whose outputs 2b, 2b + 1 are again slots of half h'.  Leaf blocks pair slots
+// 2p, 2p + 1, so they stay inside one half too.
+template <int K>
+struct SplitTraits {
+  static constexpr int kHS = 1 << (K - 1);  // slots per wavefront
+  static constexpr int kWB = kHS / 2;       // blocks per wavefront per level
+  static constexpr int kPB = kWB < 2 ? kWB : 2;  // blocks per wavefront per stage
+  static constexpr int kHB = 2 * kPB;            // blocks per stage
+  static constexpr int kNPART = kWB / kPB;       // stages per block group
+  static constexpr int kMaxPairs = 4;            // column chunks per workgroup
+  static constexpr int kSR = (kHB * kBlockBytes) / (2 * kMaxPairs * 2048);  // slots per swap round
+  static constexpr int kRounds = (kWB + kSR - 1) / kSR;
+};
+
+template <int K, int PREC, bool LI, bool LO>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
+void k_fused_pass_x2(FusedArgs a) {
+  using T = SplitTraits<K>;
+  using G = Geo<16>;
+  constexpr int SW = G::kSW;
+  constexpr int NR = G::kRows;
+  constexpr int HS = T::kHS, WB = T::kWB, PB = T::kPB, HB = T::kHB, NPART = T::kNPART;
+  constexpr int NST = ((LI ? 1 : 0) + K + (LO ? 1 : 0)) * NPART;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform per wavefront
+  const int half = wave & 1;
+  const int n = lane & 15, e = lane >> 4;
+  int64_t tile, group;
+  tile_of_block(a, tile, group);
+  const int P = (int)(blockDim.x >> 7);  // column chunks (wavefront pairs) per workgroup
+  const int64_t chunk = group * P + (wave >> 1);
+  if (chunk >= a.nchunks) return;
+  const int64_t slo = int64_t(1) << a.log_slo;
+  const int64_t hi = tile >> a.log_slo, lo = tile & (slo - 1);
+  const int64_t base = hi << (K + a.log_slo);
+  const int64_t col = (chunk << 4) + n;
+  const bool col_ok = col < a.nrhs;
+  const int qh = half * HS;  // first tile slot of this wavefront
+
+  // Stage (g, part) holds blocks h WB + part PB + i of group g at LDS position
+  // h PB + i, for both halves h: every wavefront computes PB blocks per stage.
+  __shared__ __attribute__((aligned(16))) char lds[2 * HB * kBlockBytes];
+  const int pact = (int)((a.nchunks - group * P) < P ? (a.nchunks - group * P) : P);
+  const int wact = 2 * pact;
+  auto issue_stage = [&](int sti) {
+    char *dst = lds + (sti & 1) * (HB * kBlockBytes);
+    const int g = sti / NPART, part = sti % NPART;
+    for (int c = wave; c < HB * 8; c += wact) {
+      const int pos = c >> 3;
+      const int beta = (pos / PB) * WB + part * PB + (pos % PB);
+      const char *bp;
+      const float *sp;
+      const int64_t bi = group_block<K, LI>(a, tile, g, beta, bp, sp);
+      const char *src = bp + bi * kBlockBytes + (c & 7) * 1024 + lane * 16;
+      __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)(dst + c * 1024),
+                                       16, 0, 0);
+    }
+  };
+  auto block_scale = [&](int g, int beta) {
+    if constexpr (PREC != kF16) return 1.f;
+    const char *bp;
+    const float *sp;
+    const int64_t bi = group_block<K, LI>(a, tile, g, beta, bp, sp);
+    return sp[bi];
+  };
+  issue_stage(0);
+
+  float st[HS][SW];
+
+  // ---- inputs at depth 0: tile slots qh .. qh + HS - 1
+  static_for<HS>([&](auto J) {
+    constexpr int j = J;
+    const int64_t q = qh + j;
+    const int64_t slot = a.mode_si ? base + (q << a.log_slo) + lo : base + (lo << K) + q;
+    if constexpr (LI) {
+      const f32x2 *g = static_cast<const f32x2 *>(a.in);
+      static_for<NR>([&](auto RHO) {
+        constexpr int rho = RHO;
+        f32x2 v = {0.f, 0.f};
+        if (col_ok) v = __builtin_nontemporal_load(&g[(slot * kRank + G::row(e, rho)) * a.ld + col]);
+        st[j][rho] = v.x;
+        st[j][NR + rho] = v.y;
+      });
+    } else {
+      const int64_t tr = ((slot & (a.m - 1)) << a.log_m) | (slot >> a.log_m);
+      const int64_t src = a.in_kind == kInMiddle ? tr : slot;
+      const f32x4 *p = static_cast<const f32x4 *>(a.in) + ((chunk * a.nslots + src) * 8) * 16 + n;
+      static_for<NR / 2>([&](auto JJ) {
+        constexpr int jj = JJ;
+        const f32x4 v = __builtin_nontemporal_load(p + G::pair(e, jj) * 16);
+        st[j][2 * jj] = v.x;
+        st[j][NR + 2 * jj] = v.y;
+        st[j][2 * jj + 1] = v.z;
+        st[j][NR + 2 * jj + 1] = v.w;
+      });
+    }
+  });
+  if (!LI && a.in_kind == kInMiddle) {
+    static_for<HS>([&](auto J) {
+      constexpr int j = J;
+      const int64_t q = qh + j;
+      const int64_t slot = a.mode_si ? base + (q << a.log_slo) + lo : base + (lo << K) + q;
+      const f32x4 s4 = reinterpret_cast<const f32x4 *>(a.Sm + slot * kRank)[e];
+      static_for<4>([&](auto V) {
+        const float sc = pick4(s4, V);
+        st[j][V] *= sc;
+        st[j][NR + V] *= sc;
+      });
+    });
+  }
+
+  // block h WB + bw of group g (bw < WB), staged in LDS
+  auto step = [&](auto GG, auto BW, const float *x0, const float *x1, float *y0, float *y1) {
+    constexpr int g = GG, bw = BW;
+    constexpr int sti = g * NPART + bw / PB;
+    const char *blk = lds + (sti & 1) * (HB * kBlockBytes) + (half * PB + bw % PB) * kBlockBytes;
+    BlockA A;
+    static_for<8>([&](auto V) {
+      A.v[V] = reinterpret_cast<const u32x4 *>(blk + V * 1024)[lane];
+    });
+    block_op<16, PREC>(A, block_scale(g, half * WB + bw), x0, x1, y0, y1);
+  };
+  auto stage_begin = [&](auto STI) {
+    constexpr int sti = STI;
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if constexpr (sti + 1 < NST) issue_stage(sti + 1);
+  };
+  // leaf blocks: slots 2 bw, 2 bw + 1 of this half
+  auto pair_group = [&](auto GG) {
+    constexpr int g = GG;
+    static_for<WB>([&](auto BW) {
+      constexpr int bw = BW;
+      if constexpr (bw % PB == 0) stage_begin(std::integral_constant<int, g * NPART + bw / PB>{});
+      float t0[SW], t1[SW];
+      step(GG, BW, st[2 * bw], st[2 * bw + 1], t0, t1);
+      static_for<SW>([&](auto JJ) {
+        st[2 * bw][JJ] = t0[JJ];
+        st[2 * bw + 1][JJ] = t1[JJ];
+      });
+    });
+  };
+
+  if constexpr (LI) pair_group(std::integral_constant<int, 0>{});
+
+  // ---- levels 0 .. K-2 inside the half
+  static_for<K - 1>([&](auto D) {
+    constexpr int d = D;
+    constexpr int g = (LI ? 1 : 0) + d;
+    float nx[HS][SW];
+    static_for<WB>([&](auto BW) {
+      constexpr int bw = BW;
+      if constexpr (bw % PB == 0) stage_begin(std::integral_constant<int, g * NPART + bw / PB>{});
+      constexpr int ap = bw >> d, b = bw & ((1 << d) - 1);
+      constexpr int qi0 = (2 * ap) * (1 << d) + b, qi1 = qi0 + (1 << d);
+      constexpr int qo0 = ap * (2 << d) + 2 * b, qo1 = qo0 + 1;
+      step(std::integral_constant<int, g>{}, BW, st[qi0], st[qi1], nx[qo0], nx[qo1]);
+    });
+    static_for<HS>([&](auto Q) {
+      static_for<SW>([&](auto JJ) { st[Q][JJ] = nx[Q][JJ]; });
+    });
+  });
+
+  // ---- swap halves through the LDS buffer of the stage just finished: kp[k]
+  // is the operand this wavefront keeps for block half WB + k, rv[k] the one it
+  // receives from the other half
+  constexpr int gl = (LI ? 1 : 0) + K - 1;  // group of the last level
+  constexpr int st_last = gl * NPART - 1;   // last stage before it
+  float kp[WB][SW], rv[WB][SW];
+  {
+    char *xb = lds + (st_last & 1) * (HB * kBlockBytes);
+    static_for<WB>([&](auto KK) {
+      constexpr int k = KK;
+      static_for<SW>([&](auto JJ) {
+        const float a0 = st[k][JJ], a1 = st[WB + k][JJ];
+        kp[k][JJ] = half ? a1 : a0;
+        st[k][JJ] = half ? a0 : a1;  // the operand sent to the other half
+      });
+    });
+    __syncthreads();  // every wavefront is done with that stage's blocks
+    static_for<T::kRounds>([&](auto R) {
+      constexpr int r0 = R * T::kSR;
+      static_for<T::kSR>([&](auto S) {
+        constexpr int k = r0 + S;
+        if constexpr (k < WB) {
+          f32x4 *w = reinterpret_cast<f32x4 *>(xb + ((wave * T::kSR + S) * 2) * 1024) + lane;
+          w[0] = f32x4{st[k][0], st[k][1], st[k][2], st[k][3]};
+          w[64] = f32x4{st[k][4], st[k][5], st[k][6], st[k][7]};
+        }
+      });
+      __syncthreads();
+      static_for<T::kSR>([&](auto S) {
+        constexpr int k = r0 + S;
+        if constexpr (k < WB) {
+          const f32x4 *rp =
+              reinterpret_cast<const f32x4 *>(xb + (((wave ^ 1) * T::kSR + S) * 2) * 1024) + lane;
+          const f32x4 u0 = rp[0], u1 = rp[64];
+          rv[k][0] = u0.x; rv[k][1] = u0.y; rv[k][2] = u0.z; rv[k][3] = u0.w;
+          rv[k][4] = u1.x; rv[k][5] = u1.y; rv[k][6] = u1.z; rv[k][7] = u1.w;
+        }
+      });
+      if constexpr (R + 1 < T::kRounds) __syncthreads();
+    });
+  }
+
+  // ---- last level: blocks b = half WB + k, inputs slots b and HS + b
+  static_for<WB>([&](auto BW) {
+    constexpr int k = BW;
+    if constexpr (k % PB == 0) stage_begin(std::integral_constant<int, gl * NPART + k / PB>{});
+    float x0[SW], x1[SW];
+    static_for<SW>([&](auto JJ) {
+      x0[JJ] = half ? rv[k][JJ] : kp[k][JJ];
+      x1[JJ] = half ? kp[k][JJ] : rv[k][JJ];
+    });
+    step(std::integral_constant<int, gl>{}, BW, x0, x1, st[2 * k], st[2 * k + 1]);
+  });
+
+  if constexpr (LO) pair_group(std::integral_constant<int, (LI ? 1 : 0) + K>{});
+
+  // ---- outputs at depth K
+  static_for<HS>([&](auto J) {
+    constexpr int j = J;
+    const int64_t q = qh + j;
+    const int64_t slot = a.mode_si ? base + (lo << K) + q : base + (q << a.log_slo) + lo;
+    if constexpr (LO) {
+      if (col_ok) {
+        f32x2 *u = static_cast<f32x2 *>(a.out);
+        static_for<NR>([&](auto RHO) {
+          constexpr int rho = RHO;
+          const f32x2 v = {st[j][rho], st[j][NR + rho]};
+          __builtin_nontemporal_store(v, &u[(slot * kRank + G::row(e, rho)) * a.ld + col]);
+        });
+      }
+    } else {
+      f32x4 *p = static_cast<f32x4 *>(a.out) + ((chunk * a.nslots + slot) * 8) * 16 + n;
+      static_for<NR / 2>([&](auto JJ) {
+        constexpr int jj = JJ;
+        const f32x4 v = {st[j][2 * jj], st[j][NR + 2 * jj], st[j][2 * jj + 1], st[j][NR + 2 * jj + 1]};
+        __builtin_nontemporal_store(v, p + G::pair(e, jj) * 16);
+      });
+    }
+  });
+}
+
 // One workgroup per (tile, group of up to kMaxWaves column chunks).
 template <int COLS, int K>
 inline int64_t waves_per_group(const FusedArgs &a) {
@@ -580,7 +841,8 @@ inline int64_t waves_per_group(const FusedArgs &a) {
 
 // Launch one pass (defined in bf_fused_<prec>.hip).
 template <int PREC>
-hipError_t launch_prec(FusedArgs a, int cols, int K, bool leaf_in, bool leaf_out, hipStream_t s);
+hipError_t launch_prec(FusedArgs a, int cols, int K, bool leaf_in, bool leaf_out, bool split,
+                       hipStream_t s);
 
 #define BF_FUSED_LAUNCH(COLS, KK, PREC, LI, LO)                                               \
   do {                                                                                        \
@@ -590,6 +852,26 @@ hipError_t launch_prec(FusedArgs a, int cols, int K, bool leaf_in, bool leaf_out
                        dim3((unsigned)(a.ntiles * a.ngroups)), dim3((unsigned)(w * 64)), 0, s, \
                        a);                                                                    \
   } while (0)
+
+#define BF_FUSED_LAUNCH_X2(KK, PREC, LI, LO)                                                  \
+  do {                                                                                        \
+    const int64_t w = a.nchunks < SplitTraits<KK>::kMaxPairs ? a.nchunks : SplitTraits<KK>::kMaxPairs; \
+    a.ngroups = (int)((a.nchunks + w - 1) / w);                                               \
+    hipLaunchKernelGGL((k_fused_pass_x2<KK, PREC, LI, LO>),                                   \
+                       dim3((unsigned)(a.ntiles * a.ngroups)), dim3((unsigned)(w * 128)), 0, s, \
+                       a);                                                                    \
+  } while (0)
+
+#define BF_FUSED_CASES_X2(KK, PREC)                            \
+  case 256 + KK * 4 + 0:                                       \
+    BF_FUSED_LAUNCH_X2(KK, PREC, false, false);                \
+    break;                                                     \
+  case 256 + KK * 4 + 2:                                       \
+    BF_FUSED_LAUNCH_X2(KK, PREC, true, false);                 \
+    break;                                                     \
+  case 256 + KK * 4 + 1:                                       \
+    BF_FUSED_LAUNCH_X2(KK, PREC, false, true);                 \
+    break;
 
 #define BF_FUSED_CASES(COLS, KK, PREC)                         \
   case (COLS / 16) * 64 + KK * 4 + 0:                          \
@@ -604,9 +886,10 @@ hipError_t launch_prec(FusedArgs a, int cols, int K, bool leaf_in, bool leaf_out
 
 #define BF_FUSED_DEFINE_LAUNCH(PREC)                                                        \
   template <>                                                                               \
-  hipError_t launch_prec<PREC>(FusedArgs a, int cols, int K, bool li, bool lo,             \
+  hipError_t launch_prec<PREC>(FusedArgs a, int cols, int K, bool li, bool lo, bool split, \
                                hipStream_t s) {                                             \
-    switch ((cols / 16) * 64 + K * 4 + (li ? 2 : 0) + (lo ? 1 : 0)) {                       \
+    const int key = split && cols == 16 ? 256 : (cols / 16) * 64;                           \
+    switch (key + K * 4 + (li ? 2 : 0) + (lo ? 1 : 0)) {                                    \
       BF_FUSED_CASES(32, 1, PREC)                                                           \
       BF_FUSED_CASES(32, 2, PREC)                                                           \
       BF_FUSED_CASES(32, 3, PREC)                                                           \
@@ -614,6 +897,8 @@ hipError_t launch_prec(FusedArgs a, int cols, int K, bool leaf_in, bool leaf_out
       BF_FUSED_CASES(16, 2, PREC)                                                           \
       BF_FUSED_CASES(16, 3, PREC)                                                           \
       BF_FUSED_CASES(16, 4, PREC)                                                           \
+      BF_FUSED_CASES_X2(3, PREC)                                                            \
+      BF_FUSED_CASES_X2(4, PREC)                                                            \
       default:                                                                              \
         return hipErrorInvalidValue;                                                        \
     }                                                                                       \

@@ -33,10 +33,12 @@ def fio4096():
     return oracle.construct_factors(kernels.fio(4096), leaf=16, r=16, method="sampling", seed=0)
 
 
-def _handle(f, prec, kmax=None, cols=None):
-    """Handle on the fused path; kmax / cols pick the pass depth and wave geometry."""
+def _handle(f, prec, kmax=None, cols=None, split=None):
+    """Handle on the fused path; kmax / cols pick the pass depth and wave geometry,
+    split the shallowest pass depth whose tiles are shared by wavefront pairs
+    (0: none)."""
     from paper_1502_01379_amd import BFHandle
-    env = {"BF_FUSED_KMAX": kmax, "BF_FUSED_COLS": cols}
+    env = {"BF_FUSED_KMAX": kmax, "BF_FUSED_COLS": cols, "BF_FUSED_SPLIT": split}
     old = {k: os.environ.get(k) for k in env}
     for k, v in env.items():
         if v is not None:
@@ -82,6 +84,43 @@ def test_fused_pass_depths_agree(dev, fio4096, cols, kmax):
     h = _handle(fio4096, "f32", kmax=kmax, cols=cols)
     u = h.apply(_dev(g, dev)).cpu().numpy()
     assert oracle.rel_err(u, ref) < TOL["f32"]
+
+
+@pytest.fixture(scope="module")
+def synth68():
+    return {L: synthetic_factors(2, 16, L, 16, seed=60 + L) for L in (6, 8)}
+
+
+@pytest.mark.parametrize("split", [3, 0])
+@pytest.mark.parametrize("L", [6, 8])
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("nrhs", [16, 33, 80, 130])
+def test_fused_split_tiles(dev, synth68, prec, nrhs, L, split):
+    # one pass per side (three levels at L = 6, four at L = 8); split = 3: the tiles
+    # are shared by two wavefronts (halves swapped through LDS before the last
+    # level), against the oracle with full and partial workgroups
+    f = synth68[L]
+    N = 16 * 2 ** L
+    g = complex_gaussian((N, nrhs), 300 + nrhs)
+    h = _handle(f, prec, kmax=4, cols=16, split=split)
+    u = h.apply(_dev(g, dev)).cpu().numpy()
+    assert oracle.rel_err(u, oracle.bf_apply(f, g)) < TOL[prec]
+    v = h.apply_adjoint(_dev(g, dev)).cpu().numpy()
+    assert oracle.rel_err(v, oracle.bf_apply_adjoint(f, g)) < TOL[prec]
+
+
+@pytest.mark.parametrize("L", [6, 8, 10])
+def test_fused_split_tree_depths(dev, L):
+    # split passes at the ends of the product (leaf in / leaf out) and after the middle
+    f = synthetic_factors(2, 16, L, 16, seed=40 + L)
+    N = 16 * 2 ** L
+    g = complex_gaussian((N, 21), L)
+    for prec in PRECS:
+        h = _handle(f, prec, kmax=4, cols=16, split=3)
+        u = h.apply(_dev(g, dev)).cpu().numpy()
+        assert oracle.rel_err(u, oracle.bf_apply(f, g)) < TOL[prec], prec
+        v = h.apply_adjoint(_dev(g, dev)).cpu().numpy()
+        assert oracle.rel_err(v, oracle.bf_apply_adjoint(f, g)) < TOL[prec], prec
 
 
 @pytest.mark.parametrize("L", [2, 4, 6, 10])
@@ -131,12 +170,15 @@ def test_full_size_2_20_256_rhs(dev):
     gd = torch.from_numpy(g).to(dev)
     cols = [0, 131, 255]
     ref = oracle.bf_apply(f, g[:, cols].astype(np.complex128))
-    for prec, wcols in [("f32", 16), ("bf16x3", 16), ("bf16x3", 32)]:
-        h = _handle(f, prec, cols=wcols)
+    for prec, wcols, kmax, split in [("f32", 16, None, None), ("f32", 16, 4, 4),
+                                     ("bf16x3", 16, None, None), ("bf16x3", 16, 4, 0),
+                                     ("bf16x3", 32, None, None), ("f16x3", 16, None, None)]:
+        h = _handle(f, prec, cols=wcols, kmax=kmax, split=split)
         u = h.apply(gd)
         torch.cuda.synchronize()
         err = oracle.rel_err(u[:, cols].cpu().numpy(), ref)
-        print(f"N=2^20 {prec} wave columns {wcols} rel err {err:.3e}", flush=True)
+        print(f"N=2^20 {prec} wave columns {wcols} kmax {kmax} split {split} rel err {err:.3e}",
+              flush=True)
         assert err < TOL[prec]
         h.close()
         del u
