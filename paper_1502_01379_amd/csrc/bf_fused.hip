@@ -118,6 +118,53 @@ float pack_block(const cd *M, int prec, int cols, char *dst) {
   return bscale;
 }
 
+// A leaf pair for the 16-column geometry: the diagonal 16 x 16 blocks
+// M_c[i][k] = M[c r + i][c r + k] of a block-diagonal 32 x 32 block, each as two
+// 16-byte pieces per lane (lane i + 16 e, value j = 4 part + rho:
+// [Re M_c, -Im M_c][i][(part, 4 e + rho)]): hi and lo halves for the split
+// precisions, part 0 and part 1 as floats for FP32.  Returns the FP16 scale.
+float pack_leaf16(const cd *M, int prec, char *dst) {
+  auto aval = [&](int c, int i, int j, int e) {
+    const cd v = M[(c * 16 + i) * 32 + c * 16 + 4 * e + (j & 3)];
+    return (j >> 2) == 0 ? v.real() : -v.imag();
+  };
+  if (prec == kF32) {
+    float *out = reinterpret_cast<float *>(dst);
+    for (int c = 0; c < 2; ++c)
+      for (int lane = 0; lane < 64; ++lane)
+        for (int j = 0; j < 8; ++j)
+          out[((c * 2 + (j >> 2)) * 64 + lane) * 4 + (j & 3)] = (float)aval(c, lane & 15, j, lane >> 4);
+    return 1.f;
+  }
+  double mx = 0;
+  for (int e = 0; e < 1024; ++e) mx = std::max(mx, std::max(std::fabs(M[e].real()), std::fabs(M[e].imag())));
+  float bscale = 1.f;
+  double pre = 1.0;
+  if (prec == kF16 && mx > 0) {
+    int ex = 0;
+    std::frexp(mx, &ex);
+    pre = std::ldexp(1.0, -ex);
+    bscale = (float)std::ldexp(1.0, ex);
+  }
+  uint16_t *out = reinterpret_cast<uint16_t *>(dst);
+  for (int c = 0; c < 2; ++c)
+    for (int lane = 0; lane < 64; ++lane)
+      for (int j = 0; j < 8; ++j) {
+        const float xf = (float)(aval(c, lane & 15, j, lane >> 4) * pre);
+        uint16_t h, l;
+        if (prec == kBF16) {
+          h = bf16_rne(xf);
+          l = bf16_rne(xf - bf16_to_f(h));
+        } else {
+          h = f16_rne(xf);
+          l = f16_rne(xf - f16_to_f(h));
+        }
+        out[((c * 2 + 0) * 64 + lane) * 8 + j] = h;
+        out[((c * 2 + 1) * 64 + lane) * 8 + j] = l;
+      }
+  return bscale;
+}
+
 }  // namespace
 
 struct FusedPass {
@@ -300,14 +347,16 @@ bf_status build_pass(bf_plan *p, const HostFactors &F, const PassPlan &pp, int p
     // last pass: leaf out (U forward, V adjoint)
     const bool in = pp.in_kind == kInUser;
     const bool use_v = in ? (pp.side == kHfwd) : (pp.side == kHadj);
-    std::vector<char> lb((size_t)ntiles * NB * kBlockBytes);
+    const int64_t lbytes = cols == 16 ? kBlockBytes / 2 : kBlockBytes;
+    std::vector<char> lb((size_t)(ntiles * NB * lbytes));
     std::vector<float> ls((size_t)ntiles * NB, 1.f);
     parallel_for(ntiles, [&](int64_t tile) {
       std::vector<cd> M(1024);
       for (int q = 0; q < NB; ++q) {
         const int64_t bi = tile * NB + q;
         leaf_block(F, use_v, in, (tile << K) + 2 * q, M.data());
-        ls[bi] = pack_block(M.data(), prec, cols, lb.data() + bi * kBlockBytes);
+        ls[bi] = cols == 16 ? pack_leaf16(M.data(), prec, lb.data() + bi * lbytes)
+                            : pack_block(M.data(), prec, cols, lb.data() + bi * lbytes);
       }
     });
     st = upload(p, fp, lb.data(), lb.size(), &fp->leaf);
@@ -367,9 +416,8 @@ bf_status fused_build(bf_plan *p, const bf_factors_host *f) {
   int cols = kDefaultCols;
   if (const char *e = std::getenv("BF_FUSED_COLS")) cols = std::atoi(e) == 32 ? 32 : 16;
   const int kcap = cols == 32 ? 3 : 4;
-  // FP32 passes are MFMA-bound and keep their best MFMA utilisation at three
-  // levels; split-precision passes are HBM-bound and gain from four (fewer passes)
-  int kmax = std::min(kcap, p->prec == BF_PREC_F32 ? 3 : 4);
+  // four-level passes (four passes per apply at L = 16) for every precision
+  int kmax = kcap;
   if (const char *e = std::getenv("BF_FUSED_KMAX")) kmax = std::max(1, std::min(kcap, std::atoi(e)));
   // passes of at least split_min levels (16-column geometry) share each tile
   // between a pair of wavefronts

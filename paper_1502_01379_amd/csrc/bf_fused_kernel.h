@@ -325,6 +325,83 @@ __device__ __forceinline__ void block_op(const BlockA &A, float bscale, const fl
   }
 }
 
+// ---- leaf blocks, 16-column geometry: one 16 x 16 product per slot ----------------
+//
+// A leaf pair is block diagonal, so each slot is multiplied by its own 16 x 16
+// block: one K step of 32 = (real parts, imaginary parts) of this lane's rows
+// 4e .. 4e+3.  Per slot c the packed block holds two 16-byte pieces per lane:
+// split precisions: hi, lo of [Re M, -Im M][i][(part, 4e + rho)];
+// FP32: the same 8 values as floats (K step s = 4 part + rho of v_mfma 16x16x4).
+template <class H8, class Hs, bool kScale>
+__device__ __forceinline__ void leaf16_split(const u32x4 ahi_u, const u32x4 alo_u, float bscale,
+                                             const float *x, float *y) {
+  float cs = 1.f, inv = 1.f;
+  if (kScale) {
+    float mx = 0.f;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) mx = fmaxf(mx, fabsf(x[j]));
+    column_scale<16>(mx, bscale, cs, inv);
+  }
+  H8 xh, xl;
+  split8<H8, Hs>(x, cs, xh, xl);  // re rows, then im rows
+  // operand of the imaginary part: (im rows, -re rows)
+  const u32x4 uh = __builtin_bit_cast(u32x4, xh), ul = __builtin_bit_cast(u32x4, xl);
+  const H8 yh = __builtin_bit_cast(H8, u32x4{uh.z, uh.w, uh.x ^ 0x80008000u, uh.y ^ 0x80008000u});
+  const H8 yl = __builtin_bit_cast(H8, u32x4{ul.z, ul.w, ul.x ^ 0x80008000u, ul.y ^ 0x80008000u});
+  const H8 ahi = __builtin_bit_cast(H8, ahi_u), alo = __builtin_bit_cast(H8, alo_u);
+  floatx4 dr = {}, di = {};
+  dr = mfma16(alo, xh, dr);
+  dr = mfma16(ahi, xl, dr);
+  dr = mfma16(ahi, xh, dr);
+  di = mfma16(alo, yh, di);
+  di = mfma16(ahi, yl, di);
+  di = mfma16(ahi, yh, di);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    y[v] = dr[v] * inv;
+    y[4 + v] = di[v] * inv;
+  }
+}
+
+__device__ __forceinline__ void leaf16_f32(const u32x4 a0, const u32x4 a1, const float *x, float *y) {
+  floatx4 dr = {}, di = {};
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+    const float a = as_f32(s < 4 ? a0 : a1, s & 3);
+    const int rho = s & 3;
+    if (s < 4) {
+      dr = __builtin_amdgcn_mfma_f32_16x16x4f32(a, x[rho], dr, 0, 0, 0);
+      di = __builtin_amdgcn_mfma_f32_16x16x4f32(a, x[4 + rho], di, 0, 0, 0);
+    } else {
+      dr = __builtin_amdgcn_mfma_f32_16x16x4f32(a, x[4 + rho], dr, 0, 0, 0);
+      di = __builtin_amdgcn_mfma_f32_16x16x4f32(a, -x[rho], di, 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    y[v] = dr[v];
+    y[4 + v] = di[v];
+  }
+}
+
+// the two slots of a leaf pair; blk points at the pair's four pieces
+template <int PREC>
+__device__ __forceinline__ void leaf_pair16(const char *blk, int lane, float bscale, const float *x0,
+                                            const float *x1, float *y0, float *y1) {
+  const u32x4 *b = reinterpret_cast<const u32x4 *>(blk) + lane;
+  const u32x4 p0 = b[0], p1 = b[64], p2 = b[128], p3 = b[192];
+  if constexpr (PREC == kF32) {
+    leaf16_f32(p0, p1, x0, y0);
+    leaf16_f32(p2, p3, x1, y1);
+  } else if constexpr (PREC == kBF16) {
+    leaf16_split<bf16x8, __bf16, false>(p0, p1, 1.f, x0, y0);
+    leaf16_split<bf16x8, __bf16, false>(p2, p3, 1.f, x1, y1);
+  } else {
+    leaf16_split<halfx8, _Float16, true>(p0, p1, bscale, x0, y0);
+    leaf16_split<halfx8, _Float16, true>(p2, p3, bscale, x1, y1);
+  }
+}
+
 // ---- geometry: which slot rows a lane holds ----------------------------------------
 template <int COLS>
 struct Geo;
@@ -356,21 +433,31 @@ struct PassTraits {
   static constexpr int kStageBlocks = (1 << (K - 1)) < 4 ? (1 << (K - 1)) : 4;
 };
 
-// Block index of block beta (0 .. 2^(K-1) - 1) of block group g: leaf-in (if
-// LI), levels 0 .. K-1, leaf-out (if LO).
-template <int K, bool LI>
-__device__ __forceinline__ int64_t group_block(const FusedArgs &a, int64_t tile, int g, int beta,
-                                               const char *&base_ptr, const float *&scale_ptr) {
+// Packed bytes of one leaf pair: a block-diagonal 32 x 32 block (32 columns per
+// wavefront) or two 16 x 16 blocks (16 columns per wavefront).
+template <int COLS>
+constexpr int kLeafBytes = COLS == 16 ? kBlockBytes / 2 : kBlockBytes;
+
+// Block beta (0 .. 2^(K-1) - 1) of block group g: leaf-in (if LI), levels
+// 0 .. K-1, leaf-out (if LO).  Returns its packed bytes and its FP16 scale slot.
+template <int COLS, int K, bool LI>
+__device__ __forceinline__ const char *group_block(const FusedArgs &a, int64_t tile, int g, int beta,
+                                                   const float *&scale) {
   constexpr int NB = 1 << (K - 1);
   const int d = g - (LI ? 1 : 0);
   if (d < 0 || d >= K) {
-    base_ptr = a.leaf;
-    scale_ptr = a.lscale;
-    return tile * NB + beta;
+    const int64_t bi = tile * NB + beta;
+    scale = a.lscale ? a.lscale + bi : nullptr;
+    return a.leaf + bi * kLeafBytes<COLS>;
   }
-  base_ptr = a.fac;
-  scale_ptr = a.fscale;
-  return ((int64_t)d * a.ntiles + tile) * NB + beta;
+  const int64_t bi = ((int64_t)d * a.ntiles + tile) * NB + beta;
+  scale = a.fscale ? a.fscale + bi : nullptr;
+  return a.fac + bi * kBlockBytes;
+}
+
+template <int K, bool LI, bool LO>
+__device__ __forceinline__ constexpr bool is_leaf_group(int g) {
+  return (LI && g == 0) || (LO && g == (LI ? 1 : 0) + K);
 }
 
 // Workgroup -> (tile, group of column chunks).  Workgroups are dispatched to the
@@ -429,21 +516,20 @@ void k_fused_pass(FusedArgs a) {
   auto issue_stage = [&](int sti) {
     char *dst = lds + (sti & 1) * (HB * kBlockBytes);
     const int g = sti / NPART, b0 = (sti % NPART) * HB;
-    for (int c = wave; c < HB * 8; c += wact) {
-      const char *bp;
+    const int lp = is_leaf_group<K, LI, LO>(g) ? kLeafBytes<COLS> / 1024 : 8;  // pieces per block
+    for (int c = wave; c < HB * lp; c += wact) {
+      const int blk = c / lp, piece = c - blk * lp;
       const float *sp;
-      const int64_t bi = group_block<K, LI>(a, tile, g, b0 + (c >> 3), bp, sp);
-      const char *src = bp + bi * kBlockBytes + (c & 7) * 1024 + lane * 16;
-      __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)(dst + c * 1024),
-                                       16, 0, 0);
+      const char *src = group_block<COLS, K, LI>(a, tile, g, b0 + blk, sp) + piece * 1024 + lane * 16;
+      __builtin_amdgcn_global_load_lds(
+          src, (__attribute__((address_space(3))) void *)(dst + blk * kBlockBytes + piece * 1024), 16, 0, 0);
     }
   };
   auto block_scale = [&](int g, int beta) {
     if constexpr (PREC != kF16) return 1.f;
-    const char *bp;
     const float *sp;
-    const int64_t bi = group_block<K, LI>(a, tile, g, beta, bp, sp);
-    return sp[bi];
+    (void)group_block<COLS, K, LI>(a, tile, g, beta, sp);
+    return *sp;
   };
   issue_stage(0);
 
@@ -502,11 +588,15 @@ void k_fused_pass(FusedArgs a) {
     constexpr int g = G, beta = BETA;
     constexpr int sti = g * NPART + beta / HB;
     const char *blk = lds + (sti & 1) * (HB * kBlockBytes) + (beta % HB) * kBlockBytes;
-    BlockA A;
-    static_for<8>([&](auto V) {
-      A.v[V] = reinterpret_cast<const u32x4 *>(blk + V * 1024)[lane];
-    });
-    block_op<COLS, PREC>(A, block_scale(g, beta), x0, x1, y0, y1);
+    if constexpr (COLS == 16 && is_leaf_group<K, LI, LO>(g)) {
+      leaf_pair16<PREC>(blk, lane, block_scale(g, beta), x0, x1, y0, y1);
+    } else {
+      BlockA A;
+      static_for<8>([&](auto V) {
+        A.v[V] = reinterpret_cast<const u32x4 *>(blk + V * 1024)[lane];
+      });
+      block_op<COLS, PREC>(A, block_scale(g, beta), x0, x1, y0, y1);
+    }
   };
   // entering stage sti: its blocks have landed in LDS, the previous stage is done
   // everywhere, and the next stage's copy starts
@@ -590,6 +680,11 @@ void k_fused_pass(FusedArgs a) {
 // of b >= 2^(K-2)), and wavefront h' then computes the blocks b = h' 2^(K-2) + k,
 // whose outputs 2b, 2b + 1 are again slots of half h'.  Leaf blocks pair slots
 // 2p, 2p + 1, so they stay inside one half too.
+// Staging of the split passes: blocks stream into two LDS buffers of one stage
+// each, one stage ahead of the stage being computed; the swap of halves has an
+// LDS region of its own.  Workgroups hold 1, 2 or 4 column chunks (2, 4 or 8
+// wavefronts); a wavefront pair past the last chunk stays resident, loading and
+// storing nothing, and takes its share of the block copies.
 template <int K>
 struct SplitTraits {
   static constexpr int kHS = 1 << (K - 1);  // slots per wavefront
@@ -598,8 +693,10 @@ struct SplitTraits {
   static constexpr int kHB = 2 * kPB;            // blocks per stage
   static constexpr int kNPART = kWB / kPB;       // stages per block group
   static constexpr int kMaxPairs = 4;            // column chunks per workgroup
-  static constexpr int kSR = (kHB * kBlockBytes) / (2 * kMaxPairs * 2048);  // slots per swap round
+  static constexpr int kSwapBytes = 16 * 1024;
+  static constexpr int kSR = kSwapBytes / (2 * kMaxPairs * 2048);  // slots per swap round
   static constexpr int kRounds = (kWB + kSR - 1) / kSR;
+  static constexpr int kLdsBytes = 2 * kHB * kBlockBytes + kSwapBytes;
 };
 
 template <int K, int PREC, bool LI, bool LO>
@@ -617,41 +714,38 @@ void k_fused_pass_x2(FusedArgs a) {
   const int n = lane & 15, e = lane >> 4;
   int64_t tile, group;
   tile_of_block(a, tile, group);
-  const int P = (int)(blockDim.x >> 7);  // column chunks (wavefront pairs) per workgroup
-  const int64_t chunk = group * P + (wave >> 1);
-  if (chunk >= a.nchunks) return;
+  const int W = (int)(blockDim.x >> 6);  // 2, 4 or 8 wavefronts
+  const int64_t chunk = group * (W >> 1) + (wave >> 1);
+  const bool active = chunk < a.nchunks;
   const int64_t slo = int64_t(1) << a.log_slo;
   const int64_t hi = tile >> a.log_slo, lo = tile & (slo - 1);
   const int64_t base = hi << (K + a.log_slo);
   const int64_t col = (chunk << 4) + n;
-  const bool col_ok = col < a.nrhs;
+  const bool col_ok = active && col < a.nrhs;
   const int qh = half * HS;  // first tile slot of this wavefront
 
-  // Stage (g, part) holds blocks h WB + part PB + i of group g at LDS position
-  // h PB + i, for both halves h: every wavefront computes PB blocks per stage.
-  __shared__ __attribute__((aligned(16))) char lds[2 * HB * kBlockBytes];
-  const int pact = (int)((a.nchunks - group * P) < P ? (a.nchunks - group * P) : P);
-  const int wact = 2 * pact;
+  // Stage (g, part) holds blocks h WB + part PB + i of group g at position
+  // h PB + i of its buffer, for both halves h.
+  __shared__ __attribute__((aligned(16))) char lds[T::kLdsBytes];
+  char *const swap = lds + 2 * HB * kBlockBytes;
   auto issue_stage = [&](int sti) {
     char *dst = lds + (sti & 1) * (HB * kBlockBytes);
     const int g = sti / NPART, part = sti % NPART;
-    for (int c = wave; c < HB * 8; c += wact) {
-      const int pos = c >> 3;
+    const int lp = is_leaf_group<K, LI, LO>(g) ? kLeafBytes<16> / 1024 : 8;  // pieces per block
+    for (int c = wave; c < HB * lp; c += W) {
+      const int pos = c / lp, piece = c - pos * lp;
       const int beta = (pos / PB) * WB + part * PB + (pos % PB);
-      const char *bp;
       const float *sp;
-      const int64_t bi = group_block<K, LI>(a, tile, g, beta, bp, sp);
-      const char *src = bp + bi * kBlockBytes + (c & 7) * 1024 + lane * 16;
-      __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)(dst + c * 1024),
-                                       16, 0, 0);
+      const char *src = group_block<16, K, LI>(a, tile, g, beta, sp) + piece * 1024 + lane * 16;
+      __builtin_amdgcn_global_load_lds(
+          src, (__attribute__((address_space(3))) void *)(dst + pos * kBlockBytes + piece * 1024), 16, 0, 0);
     }
   };
   auto block_scale = [&](int g, int beta) {
     if constexpr (PREC != kF16) return 1.f;
-    const char *bp;
     const float *sp;
-    const int64_t bi = group_block<K, LI>(a, tile, g, beta, bp, sp);
-    return sp[bi];
+    (void)group_block<16, K, LI>(a, tile, g, beta, sp);
+    return *sp;
   };
   issue_stage(0);
 
@@ -677,7 +771,8 @@ void k_fused_pass_x2(FusedArgs a) {
       const f32x4 *p = static_cast<const f32x4 *>(a.in) + ((chunk * a.nslots + src) * 8) * 16 + n;
       static_for<NR / 2>([&](auto JJ) {
         constexpr int jj = JJ;
-        const f32x4 v = __builtin_nontemporal_load(p + G::pair(e, jj) * 16);
+        f32x4 v = {0.f, 0.f, 0.f, 0.f};
+        if (active) v = __builtin_nontemporal_load(p + G::pair(e, jj) * 16);
         st[j][2 * jj] = v.x;
         st[j][NR + 2 * jj] = v.y;
         st[j][2 * jj + 1] = v.z;
@@ -704,12 +799,18 @@ void k_fused_pass_x2(FusedArgs a) {
     constexpr int g = GG, bw = BW;
     constexpr int sti = g * NPART + bw / PB;
     const char *blk = lds + (sti & 1) * (HB * kBlockBytes) + (half * PB + bw % PB) * kBlockBytes;
-    BlockA A;
-    static_for<8>([&](auto V) {
-      A.v[V] = reinterpret_cast<const u32x4 *>(blk + V * 1024)[lane];
-    });
-    block_op<16, PREC>(A, block_scale(g, half * WB + bw), x0, x1, y0, y1);
+    if constexpr (is_leaf_group<K, LI, LO>(g)) {
+      leaf_pair16<PREC>(blk, lane, block_scale(g, half * WB + bw), x0, x1, y0, y1);
+    } else {
+      BlockA A;
+      static_for<8>([&](auto V) {
+        A.v[V] = reinterpret_cast<const u32x4 *>(blk + V * 1024)[lane];
+      });
+      block_op<16, PREC>(A, block_scale(g, half * WB + bw), x0, x1, y0, y1);
+    }
   };
+  // entering stage sti: its blocks have landed, every wavefront is done with
+  // stage sti - 1, whose buffer now receives stage sti + 1
   auto stage_begin = [&](auto STI) {
     constexpr int sti = STI;
     __builtin_amdgcn_s_waitcnt(0);
@@ -751,47 +852,41 @@ void k_fused_pass_x2(FusedArgs a) {
     });
   });
 
-  // ---- swap halves through the LDS buffer of the stage just finished: kp[k]
-  // is the operand this wavefront keeps for block half WB + k, rv[k] the one it
-  // receives from the other half
+  // ---- swap halves through the swap region: kp[k] is the operand this
+  // wavefront keeps for block half WB + k, rv[k] the one it receives
   constexpr int gl = (LI ? 1 : 0) + K - 1;  // group of the last level
-  constexpr int st_last = gl * NPART - 1;   // last stage before it
   float kp[WB][SW], rv[WB][SW];
-  {
-    char *xb = lds + (st_last & 1) * (HB * kBlockBytes);
-    static_for<WB>([&](auto KK) {
-      constexpr int k = KK;
-      static_for<SW>([&](auto JJ) {
-        const float a0 = st[k][JJ], a1 = st[WB + k][JJ];
-        kp[k][JJ] = half ? a1 : a0;
-        st[k][JJ] = half ? a0 : a1;  // the operand sent to the other half
-      });
+  static_for<WB>([&](auto KK) {
+    constexpr int k = KK;
+    static_for<SW>([&](auto JJ) {
+      const float a0 = st[k][JJ], a1 = st[WB + k][JJ];
+      kp[k][JJ] = half ? a1 : a0;
+      st[k][JJ] = half ? a0 : a1;  // the operand sent to the other half
     });
-    __syncthreads();  // every wavefront is done with that stage's blocks
-    static_for<T::kRounds>([&](auto R) {
-      constexpr int r0 = R * T::kSR;
-      static_for<T::kSR>([&](auto S) {
-        constexpr int k = r0 + S;
-        if constexpr (k < WB) {
-          f32x4 *w = reinterpret_cast<f32x4 *>(xb + ((wave * T::kSR + S) * 2) * 1024) + lane;
-          w[0] = f32x4{st[k][0], st[k][1], st[k][2], st[k][3]};
-          w[64] = f32x4{st[k][4], st[k][5], st[k][6], st[k][7]};
-        }
-      });
-      __syncthreads();
-      static_for<T::kSR>([&](auto S) {
-        constexpr int k = r0 + S;
-        if constexpr (k < WB) {
-          const f32x4 *rp =
-              reinterpret_cast<const f32x4 *>(xb + (((wave ^ 1) * T::kSR + S) * 2) * 1024) + lane;
-          const f32x4 u0 = rp[0], u1 = rp[64];
-          rv[k][0] = u0.x; rv[k][1] = u0.y; rv[k][2] = u0.z; rv[k][3] = u0.w;
-          rv[k][4] = u1.x; rv[k][5] = u1.y; rv[k][6] = u1.z; rv[k][7] = u1.w;
-        }
-      });
-      if constexpr (R + 1 < T::kRounds) __syncthreads();
+  });
+  static_for<T::kRounds>([&](auto R) {
+    constexpr int r0 = R * T::kSR;
+    if constexpr (R > 0) __syncthreads();  // the previous round's reads are done
+    static_for<T::kSR>([&](auto S) {
+      constexpr int k = r0 + S;
+      if constexpr (k < WB) {
+        f32x4 *w = reinterpret_cast<f32x4 *>(swap + ((wave * T::kSR + S) * 2) * 1024) + lane;
+        w[0] = f32x4{st[k][0], st[k][1], st[k][2], st[k][3]};
+        w[64] = f32x4{st[k][4], st[k][5], st[k][6], st[k][7]};
+      }
     });
-  }
+    __syncthreads();
+    static_for<T::kSR>([&](auto S) {
+      constexpr int k = r0 + S;
+      if constexpr (k < WB) {
+        const f32x4 *rp =
+            reinterpret_cast<const f32x4 *>(swap + (((wave ^ 1) * T::kSR + S) * 2) * 1024) + lane;
+        const f32x4 u0 = rp[0], u1 = rp[64];
+        rv[k][0] = u0.x; rv[k][1] = u0.y; rv[k][2] = u0.z; rv[k][3] = u0.w;
+        rv[k][4] = u1.x; rv[k][5] = u1.y; rv[k][6] = u1.z; rv[k][7] = u1.w;
+      }
+    });
+  });
 
   // ---- last level: blocks b = half WB + k, inputs slots b and HS + b
   static_for<WB>([&](auto BW) {
@@ -808,6 +903,7 @@ void k_fused_pass_x2(FusedArgs a) {
   if constexpr (LO) pair_group(std::integral_constant<int, (LI ? 1 : 0) + K>{});
 
   // ---- outputs at depth K
+  if (!active) return;
   static_for<HS>([&](auto J) {
     constexpr int j = J;
     const int64_t q = qh + j;
@@ -855,7 +951,7 @@ hipError_t launch_prec(FusedArgs a, int cols, int K, bool leaf_in, bool leaf_out
 
 #define BF_FUSED_LAUNCH_X2(KK, PREC, LI, LO)                                                  \
   do {                                                                                        \
-    const int64_t w = a.nchunks < SplitTraits<KK>::kMaxPairs ? a.nchunks : SplitTraits<KK>::kMaxPairs; \
+    const int64_t w = a.nchunks >= 4 ? 4 : a.nchunks >= 2 ? 2 : 1;                            \
     a.ngroups = (int)((a.nchunks + w - 1) / w);                                               \
     hipLaunchKernelGGL((k_fused_pass_x2<KK, PREC, LI, LO>),                                   \
                        dim3((unsigned)(a.ntiles * a.ngroups)), dim3((unsigned)(w * 128)), 0, s, \
