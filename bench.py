@@ -103,6 +103,24 @@ def pass_work(name, L, r, leaf, nrhs, K, has_leaf, has_middle):
     return flops, 2 * act + fac + mid
 
 
+def profile_traffic(key):
+    """HBM bytes per launch of one pass kernel from the committed rocprofv3 counter
+    summaries (FETCH_SIZE and WRITE_SIZE, scaled by a copy kernel of known size),
+    or None when no summary covers it or the kernel source changed since."""
+    import glob
+    import hashlib
+    here = os.path.dirname(os.path.abspath(__file__))
+    src = os.path.join(here, "paper_1502_01379_amd", "csrc", "bf_fused_kernel.h")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    for path in sorted(glob.glob(os.path.join(here, "profiles", "*.txt"))):
+        for line in open(path):
+            if line.startswith("traffic: "):
+                rec = json.loads(line[len("traffic: "):])
+                if rec.get("kernel_source_sha256") == sha and key in rec.get("bytes", {}):
+                    return float(rec["bytes"][key])
+    return None
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -202,7 +220,9 @@ def main():
         roof = {"bound": "hbm", "achieved": bytes_ / (avg_ms * 1e-3) / 1e9,
                 "peak": HBM_PEAK_GBS, "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
+    prec_code = {"f32": 0, "bf16x3": 1, "f16x3": 2}[args.precision]
+    roof["traffic"] = profile_traffic(f"{K},{prec_code},{int(l_hi == L and parts[1] == 'H')},"
+                                      f"{int(l_hi == L and parts[1] == 'G')}")
     roof["kernel"] = name
     roof["avg_launch_ms"] = avg_ms
     roof["launches"] = launches
