@@ -50,10 +50,12 @@ def parse():
 
 
 def bench_backward(args):
-    """bf_backward on the differentiation workload: N = 2^log2n, r = 16, nrhs columns."""
+    """bf_backward (gradients of every factor block and of g) at N = 2^log2n, r = 16,
+    nrhs columns, FP32; recomputing the states inside each pass (the default) and
+    keeping every state (BF_BWD_STORE_ALL)."""
     import torch
     from bf_inputs import complex_gaussian, synthetic_factors
-    from paper_1502_01379_amd import BFHandle, BF_BWD_RECOMPUTE
+    from paper_1502_01379_amd import BFHandle, BF_BWD_RECOMPUTE, BF_BWD_STORE_ALL
     dev = torch.device("cuda:0")
     L = args.log2n - 4
     N = 16 * 2 ** L
@@ -61,24 +63,32 @@ def bench_backward(args):
     g = torch.from_numpy(complex_gaussian((N, args.nrhs), 31, dtype=np.complex64)).to(dev)
     gu = torch.from_numpy(complex_gaussian((N, args.nrhs), 32, dtype=np.complex64)).to(dev)
     h = BFHandle(f, args.precision)
-    for _ in range(args.warmup):
-        h.backward(g, gu, flags=BF_BWD_RECOMPUTE)
-    torch.cuda.synchronize()
-    h.set_profiling(True)
-    h.kernel_times(reset=True)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(args.steps):
-        h.backward(g, gu, flags=BF_BWD_RECOMPUTE)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / args.steps
-    kt = h.kernel_times(reset=True)
-    top = sorted(kt.items(), key=lambda kv: -kv[1][0])[:8]
-    out = {"metric": "bf_backward ms (grad of every factor block and of g)", "value": ms,
-           "unit": "ms", "higher_is_better": False, "precision": args.precision,
-           "config": {"N": N, "L": L, "r": 16, "nrhs": args.nrhs},
-           "top_kernels_ms_per_call": {k: v[0] / args.steps for k, v in top}}
+    modes = {}
+    for mode, flags in (("recompute", BF_BWD_RECOMPUTE), ("store_all", BF_BWD_STORE_ALL)):
+        for _ in range(args.warmup):
+            h.backward(g, gu, flags=flags)
+        torch.cuda.synchronize()
+        h.set_profiling(True)
+        h.kernel_times(reset=True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            h.backward(g, gu, flags=flags)
+        e1.record()
+        torch.cuda.synchronize()
+        h.set_profiling(False)
+        kt = h.kernel_times(reset=True)
+        top = sorted(kt.items(), key=lambda kv: -kv[1][0])[:10]
+        modes[mode] = {"ms": e0.elapsed_time(e1) / args.steps,
+                       "top_kernels_ms_per_step": {k: v[0] / args.steps for k, v in top},
+                       "launches_per_step": sum(v[1] for v in kt.values()) / args.steps}
+        print(f"[bench] backward {mode}: {modes[mode]['ms']:.3f} ms", file=sys.stderr, flush=True)
+    out = {"metric": "bf_backward ms (gradients of every factor block and of g)",
+           "value": modes["recompute"]["ms"], "unit": "ms", "higher_is_better": False,
+           "precision": args.precision, "data": "synthetic",
+           "config": {"workload": f"1D FIO-shaped factorization, N=2^{args.log2n}, leaf 16, r=16, "
+                                  f"{args.nrhs} RHS", "N": N, "L": L, "r": 16, "nrhs": args.nrhs},
+           "modes": modes}
     print(json.dumps(out), flush=True)
 
 

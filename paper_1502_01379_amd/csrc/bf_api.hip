@@ -406,10 +406,137 @@ bf_status bf_apply_adjoint(bf_handle p, const void *w, void *v, int64_t nrhs, in
 
 // Backward pass.  The forward chain is a_0 = (V^L)^* g, a_t = op_t(a_{t-1}) for
 // t = 1 .. 2h+1 (H levels, middle, G levels), u = U^L a_{2h+1}.  Going back, the
-// gradient of op_t needs its input a_{t-1} and the incoming delta_t; delta_{t-1}
-// is the adjoint of op_t applied to delta_t.  With BF_BWD_RECOMPUTE only every
-// kc-th activation is kept and the kc-1 between two kept ones are recomputed
-// when their segment is reached.
+// gradient of op_t needs its input a_{t-1} and the incoming delta_t (the
+// gradient with respect to a_t); delta_{t-1} is the adjoint of op_t applied to
+// delta_t.  The adjoint chain b_{-1} = delta_u, b_k = adj_op_k(b_{k-1}) gives
+// b_k = delta_{2h+1-k}.
+
+namespace {
+
+#define BWD_LAUNCH(name, call)                                                                      \
+  do {                                                                                              \
+    bfly::prof_begin(p, name, s);                                                                   \
+    hipError_t e_ = (call);                                                                         \
+    bfly::prof_end(p, s);                                                                           \
+    if (e_ != hipSuccess) return fail(p, BF_ERR_HIP, std::string(name) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// Fused-path handles: the forward and the adjoint chains run as the apply's
+// multi-level passes (FP32) that also leave a copy of the state after every
+// level; the block gradients are MFMA contractions of those copies.  With
+// BF_BWD_STORE_ALL every a_t is kept; otherwise only the pass boundaries are
+// kept and, before each adjoint pass, the forward pass it mirrors runs again to
+// restore the states between them.  The b_k live in a ring of six buffers: an
+// adjoint pass reads one and writes at most five, and the gradients of the
+// levels it mirrors are taken before the next pass.
+bf_status backward_fused(bf_plan *p, const void *g, const void *grad_u, void *grad_g,
+                         const bf_factor_grads *grads, int64_t nrhs, int64_t ld, bool store_all,
+                         hipStream_t s) {
+  bf_status st;
+  if (!p->bwd_ready && (st = bfly::fused_build_backward(p, s)) != BF_OK) return st;
+  const int h = p->h, nact = 2 * h + 2;
+  const auto &F = p->fwd_ops;
+  const auto &FP = p->bwd_fwd, &AP = p->bwd_adj;
+  const int np = (int)FP.size();
+  // pass j reads a_{tin[j]} (-1: the user vector) and leaves a_{td0[j] + d} after d levels
+  auto positions = [&](const std::vector<bfly::FusedPass *> &list, std::vector<int> &tin,
+                       std::vector<int> &td0) {
+    int t = -1;
+    for (const auto *fp : list) {
+      const bfly::PassShape sh = bfly::fused_pass_shape(fp);
+      tin.push_back(t);
+      td0.push_back((sh.li || sh.mid) ? t + 1 : t);
+      t = td0.back() + sh.K;
+    }
+    return t;
+  };
+  std::vector<int> tin, td0, tinb, td0b;
+  if (positions(FP, tin, td0) != nact - 1 || positions(AP, tinb, td0b) != nact - 1)
+    return fail(p, BF_ERR_UNSUPPORTED, "backward pass plan does not cover the chain");
+  // buffers: kept a_t, the states inside one pass (recompute), the b ring, and the
+  // leaf-out result when grad_g is not wanted
+  std::vector<int> abuf(nact, -1);
+  int nb = 0;
+  for (int j = 0; j < np; ++j) {
+    const bfly::PassShape sh = bfly::fused_pass_shape(FP[j]);
+    for (int d = 0; d <= sh.K; ++d) {
+      const int t = td0[j] + d;
+      if (t < 0 || abuf[t] >= 0) continue;
+      if (store_all || d == sh.K || (d == 0 && (sh.li || sh.mid))) abuf[t] = nb++;
+    }
+  }
+  const int seg0 = nb;
+  if (!store_all) nb += 3;  // depths 1 .. K-1 of one pass, K <= 4
+  const int ring0 = nb;
+  nb += 6;
+  const size_t ab = act_bytes(p, nrhs);
+  const size_t user_bytes = (size_t)((p->N - 1) * ld + nrhs) * 8;
+  if ((st = ensure_ws(p, (size_t)nb * ab + (grad_g ? 0 : user_bytes))) != BF_OK) return st;
+  char *const ws = static_cast<char *>(p->ws);
+  auto buf = [&](int i) { return static_cast<void *>(ws + (size_t)i * ab); };
+  std::vector<void *> aptr(nact, nullptr);
+  for (int t = 0; t < nact; ++t)
+    if (abuf[t] >= 0) aptr[t] = buf(abuf[t]);
+  auto bptr = [&](int k) { return buf(ring0 + k % 6); };
+  void *gout = grad_g ? grad_g : static_cast<void *>(ws + (size_t)nb * ab);
+
+  // forward pass j with copies of the states that have a buffer
+  auto run_forward = [&](int j, const char *tag) -> bf_status {
+    const bfly::PassShape sh = bfly::fused_pass_shape(FP[j]);
+    void *lvl[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    for (int d = (sh.li || sh.mid) ? 0 : 1; d < sh.K; ++d) lvl[d] = aptr[td0[j] + d];
+    const void *in = tin[j] < 0 ? g : aptr[tin[j]];
+    BWD_LAUNCH((*sh.name + tag).c_str(),
+               bfly::fused_run_pass(p, FP[j], in, aptr[td0[j] + sh.K], lvl, nrhs, ld, s));
+    return BF_OK;
+  };
+  for (int j = 0; j < np; ++j)
+    if ((st = run_forward(j, "")) != BF_OK) return st;
+
+  // U^L: grad_UL = sum delta_u a_{2h+1}^*
+  if (grads && grads->UL)
+    BWD_LAUNCH("grad_UL", bfly::launch_grad_leaf_mfma(p, grad_u, ld, aptr[nact - 1], grads->UL, nrhs, s));
+
+  for (int i = 0; i < np; ++i) {
+    const int j = np - 1 - i;  // the forward pass over the same levels
+    const bfly::PassShape fs = bfly::fused_pass_shape(FP[j]);
+    if (!store_all) {
+      for (int d = 1; d < fs.K; ++d) aptr[td0[j] + d] = buf(seg0 + d - 1);
+      if ((st = run_forward(j, "_recompute")) != BF_OK) return st;
+    }
+    const bfly::PassShape as = bfly::fused_pass_shape(AP[i]);
+    void *lvl[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    for (int d = (as.li || as.mid) ? 0 : 1; d < as.K; ++d) lvl[d] = bptr(td0b[i] + d);
+    if (as.lo) lvl[as.K] = bptr(td0b[i] + as.K);
+    const void *in = tinb[i] < 0 ? grad_u : bptr(tinb[i]);
+    void *out = as.lo ? gout : bptr(td0b[i] + as.K);
+    BWD_LAUNCH(as.name->c_str(), bfly::fused_run_pass(p, AP[i], in, out, lvl, nrhs, ld, s));
+    // gradients of the ops of forward pass j
+    for (int t = td0[j] + ((fs.li || fs.mid) ? 0 : 1); t <= td0[j] + fs.K; ++t) {
+      void *dout = bptr(2 * h + 1 - t);
+      if (t == 0) {
+        if (grads && grads->VL) BWD_LAUNCH("grad_VL", bfly::launch_grad_leaf_mfma(p, g, ld, dout, grads->VL, nrhs, s));
+      } else if (t == h + 1) {
+        if (grads && grads->S) BWD_LAUNCH("grad_S", bfly::launch_middle_grad(p, dout, aptr[h], grads->S, nrhs, s));
+      } else {
+        const bfly::LevelOp &op = F[t];
+        const bool is_g = t > h + 1;
+        void *const *arr = grads ? (is_g ? grads->G : grads->H) : nullptr;
+        void *dst = arr ? arr[op.level - h] : nullptr;
+        if (!dst) continue;
+        const void *xin = aptr[t - 1];
+        if (is_g)
+          BWD_LAUNCH("grad_G", bfly::launch_grad_level_mfma(p, op, dout, xin, dst, nrhs, s));
+        else
+          BWD_LAUNCH("grad_H", bfly::launch_grad_level_mfma(p, op, xin, dout, dst, nrhs, s));
+      }
+    }
+  }
+  return BF_OK;
+}
+
+}  // namespace
+
 bf_status bf_backward(bf_handle p, const void *g, const void *grad_u, void *grad_g,
                       const bf_factor_grads *grads, int64_t nrhs, int64_t ld, uint32_t flags,
                       hipStream_t s) {
@@ -423,6 +550,12 @@ bf_status bf_backward(bf_handle p, const void *g, const void *grad_u, void *grad
   }
   if (flags & ~BF_BWD_STORE_ALL) return fail(p, BF_ERR_INVALID_ARG, "unknown flags");
   const bool store_all = (flags & BF_BWD_STORE_ALL) != 0;
+  if (p->path == 1 && p->cs == 4)
+    return backward_fused(p, g, grad_u, grad_g, grads, nrhs, ld, store_all, s);
+
+  // per-level kernels: the forward chain level by level, every kc-th activation
+  // kept (all of them with BF_BWD_STORE_ALL) and the ones between recomputed when
+  // their segment is reached
   const int h = p->h;
   const int nact = 2 * h + 2;          // a_0 .. a_{2h+1}
   const int kc = store_all ? 1 : 4;    // checkpoint spacing
@@ -437,32 +570,9 @@ bf_status bf_backward(bf_handle p, const void *g, const void *grad_u, void *grad
   char *dbuf[2] = {bufp(nckpt + nseg), bufp(nckpt + nseg + 1)};
   const auto &F = p->fwd_ops;   // F[0] leaf_in, F[1..2h+1], F[2h+2] leaf_out
   const auto &A = p->adj_ops;   // A[0] leaf_in(U^*), A[k] adjoint of F[2h+2-k]
-  hipError_t e;
-  // on the fused path every butterfly level runs as a one-level FP32 MFMA pass and
-  // the block gradients as MFMA contractions; other ops use the per-level kernels
-  if (p->path == 1 && !p->bwd_ready && p->cs == 4) {
-    if ((st = bfly::fused_build_backward(p, s)) != BF_OK) return st;
-  }
-  const bool fast = p->bwd_ready;
   auto run_op = [&](bool adj, int t, const void *in, void *out) -> hipError_t {
-    const LevelOp &op = adj ? A[t] : F[t];
-    const bfly::FusedPass *fp = fast ? (adj ? p->bwd_adj[t] : p->bwd_fwd[t]) : nullptr;
-    if (fp) return bfly::fused_run_level(p, fp, in, out, nrhs, s);
-    if (fast && (op.kind == LevelOp::kLeafIn || op.kind == LevelOp::kLeafOut))
-      return bfly::launch_leaf16(p, op, in, out, nrhs, ld, s);
-    return bfly::launch_level_op(p, op, in, ld, out, ld, nrhs, s);
+    return bfly::launch_level_op(p, adj ? A[t] : F[t], in, ld, out, ld, nrhs, s);
   };
-  auto run_grad = [&](const LevelOp &op, const void *X, const void *Y, void *dst) -> hipError_t {
-    if (fast) return bfly::launch_grad_level_mfma(p, op, X, Y, dst, nrhs, s);
-    return bfly::launch_level_grad(p, op, X, Y, dst, nrhs, s);
-  };
-#define BWD_LAUNCH(name, call)                                                         \
-  do {                                                                                 \
-    bfly::prof_begin(p, name, s);                                                      \
-    e = (call);                                                                        \
-    bfly::prof_end(p, s);                                                              \
-    if (e != hipSuccess) return fail(p, BF_ERR_HIP, std::string(name) + ": " + hipGetErrorString(e)); \
-  } while (0)
 
   // forward sweep keeping checkpoints
   {
@@ -495,14 +605,11 @@ bf_status bf_backward(bf_handle p, const void *g, const void *grad_u, void *grad
     return hipSuccess;
   };
 
+  hipError_t e;
   const int T = nact - 1;  // index of a_{2h+1}
   // U^L: grad_UL = sum delta_u a_T^*, delta_T = (U^L)^* delta_u
   if ((e = ensure_seg(T)) != hipSuccess) return fail(p, BF_ERR_HIP, std::string("recompute: ") + hipGetErrorString(e));
-  auto leaf_grad = [&](const void *user, const void *a, void *dst) -> hipError_t {
-    if (fast) return bfly::launch_grad_leaf_mfma(p, user, ld, a, dst, nrhs, s);
-    return bfly::launch_leaf_grad(p, user, ld, a, dst, nrhs, s);
-  };
-  if (grads && grads->UL) BWD_LAUNCH("grad_UL", leaf_grad(grad_u, act(T), grads->UL));
+  if (grads && grads->UL) BWD_LAUNCH("grad_UL", bfly::launch_leaf_grad(p, grad_u, ld, act(T), grads->UL, nrhs, s));
   int cur_d = 0;
   BWD_LAUNCH(A[0].name.c_str(), run_op(true, 0, grad_u, dbuf[cur_d]));
   for (int t = T; t >= 1; --t) {
@@ -513,18 +620,17 @@ bf_status bf_backward(bf_handle p, const void *g, const void *grad_u, void *grad
     if (op.kind == LevelOp::kMiddle) {
       if (grads && grads->S) BWD_LAUNCH("grad_S", bfly::launch_middle_grad(p, dout, xin, grads->S, nrhs, s));
     } else {
-      const int lvl = (t <= h) ? p->L - t : t - h - 2 + h;  // H: L-1..h ; G: h..L-1
       const bool is_g = t > h + 1;
       void *dst = nullptr;
       if (grads) {
         void *const *arr = is_g ? grads->G : grads->H;
-        if (arr) dst = arr[lvl - h];
+        if (arr) dst = arr[op.level - h];
       }
       if (dst) {
         if (is_g)
-          BWD_LAUNCH("grad_G", run_grad(op, dout, xin, dst));
+          BWD_LAUNCH("grad_G", bfly::launch_level_grad(p, op, dout, xin, dst, nrhs, s));
         else
-          BWD_LAUNCH("grad_H", run_grad(op, xin, dout, dst));
+          BWD_LAUNCH("grad_H", bfly::launch_level_grad(p, op, xin, dout, dst, nrhs, s));
       }
     }
     const LevelOp &aop = A[nact - t];
@@ -532,11 +638,11 @@ bf_status bf_backward(bf_handle p, const void *g, const void *grad_u, void *grad
     cur_d ^= 1;
   }
   // V^L: grad_VL = sum g delta_0^*, grad_g = V^L delta_0
-  if (grads && grads->VL) BWD_LAUNCH("grad_VL", leaf_grad(g, dbuf[cur_d], grads->VL));
+  if (grads && grads->VL) BWD_LAUNCH("grad_VL", bfly::launch_leaf_grad(p, g, ld, dbuf[cur_d], grads->VL, nrhs, s));
   if (grad_g) BWD_LAUNCH(A[nact].name.c_str(), run_op(true, nact, dbuf[cur_d], grad_g));
-#undef BWD_LAUNCH
   return BF_OK;
 }
+#undef BWD_LAUNCH
 
 void bf_destroy(bf_handle p) { delete p; }
 

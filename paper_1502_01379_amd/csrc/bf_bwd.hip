@@ -1,9 +1,10 @@
 // Backward-pass kernels for handles on the fused path (radix 2, leaf 16, r 16).
 //
-//  * k_pack_level: packs one butterfly level of the canonical factors (device,
-//    complex64) into the per-lane A-operand order of the 16-column FP32 block
-//    product (one block per butterfly, the order a one-level fused pass reads),
-//    so the backward pass can run every level through the fused kernel.
+//  * k_pack_pass / k_pack_leaf16: pack the blocks of a K-level FP32 fused pass
+//    (butterfly blocks and leaf pairs) from the canonical factors on the device,
+//    in the per-lane A-operand order of the 16-column block products, so the
+//    backward pass runs the same fused passes as the apply in FP32.
+//  * k_grad_leaf: the gradient of the leaf blocks (two leaves per wavefront).
 //  * k_grad_level: the gradient of every block of one level,
 //        grad[2 hi + cx][lo][rx][cy r + ry] = sum_n X[strided(b,cx)][rx][n] conj(Y[contig(b,cy)][ry][n]),
 //    (grad_B = sum_n d_out x_in^* for G levels with X = d_out, Y = x_in;
@@ -38,22 +39,58 @@ __device__ __forceinline__ float block_value(const float2 *__restrict__ Fb, int6
   return part == 0 ? v.x : -v.y;
 }
 
-// one thread per (butterfly, lane, float f of the lane's 32): block layout of
-// the 16-column FP32 product: f = 16 T + s, s = 8 part + 4 c' + rho; lane (i, e)
-// with i = lane % 16, e = lane / 16; output row 16 T + i, input row 16 c' + 4 e + rho
-__global__ void k_pack_level(const float2 *__restrict__ Fb, float *__restrict__ out, int64_t nb,
-                             int64_t blo, int tconj) {
+// Blocks of a K-level FP32 pass, [depth d][tile][beta], from the canonical
+// factors: the butterfly at depth d takes tile-local slots qi0, qi0 + 2^d, whose
+// place in the level-by-level slot order is fixed by the pass's slot mode (the
+// same map the pass uses for its per-depth copies); the level's butterfly index
+// follows from the slot pattern of that level (strided or contiguous input).
+__global__ void k_pack_pass(PackPassArgs a, float *__restrict__ out) {
+  const int64_t NB = int64_t(1) << (a.K - 1);
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (t >= nb * 64 * 32) return;
+  if (t >= (int64_t)a.K * a.ntiles * NB * 2048) return;
   const int f = (int)(t & 31);
   const int lane = (int)((t >> 5) & 63);
-  const int64_t b = t >> 11;
-  const int64_t hi = b / blo, lo = b - hi * blo;
-  const int T = f >> 4, s = f & 15;
-  const int part = s >> 3, cp = (s >> 2) & 1, rho = s & 3;
+  const int64_t bi = t >> 11;
+  const int d = (int)(bi / (a.ntiles * NB));
+  const int64_t rem = bi - d * a.ntiles * NB;
+  const int64_t tile = rem / NB;
+  const int beta = (int)(rem - tile * NB);
+  const int ap = beta >> d, bb = beta & ((1 << d) - 1);
+  const int64_t q = ((int64_t)(2 * ap) << d) + bb;
+  const int64_t lo = tile & ((int64_t(1) << a.log_slo) - 1);
+  const int64_t base = (tile >> a.log_slo) << (a.K + a.log_slo);
+  const int64_t dm = (int64_t(1) << d) - 1;
+  const int64_t slot = a.mode_si ? base + ((q >> d) << (d + a.log_slo)) + (lo << d) + (q & dm)
+                                 : base + ((q & dm) << (a.K - d + a.log_slo)) + (lo << (a.K - d)) + (q >> d);
+  const PackDepth &pd = a.dep[d];
+  const int64_t blo = int64_t(1) << pd.log_blo;
+  const int64_t b = pd.contig ? (slot >> 1) : (((slot >> (pd.log_blo + 1)) << pd.log_blo) | (slot & (blo - 1)));
+  const int T = f >> 4, sidx = f & 15;
+  const int part = sidx >> 3, cp = (sidx >> 2) & 1, rho = sidx & 3;
   const int i = lane & 15, e = lane >> 4;
-  const float v = block_value(Fb, hi, lo, blo, tconj, 16 * T + i, 16 * cp + 4 * e + rho, part);
-  out[b * 2048 + ((f >> 2) * 64 + lane) * 4 + (f & 3)] = v;
+  const float v = block_value(static_cast<const float2 *>(pd.Fb), b / blo, b % blo, blo, pd.tconj,
+                              16 * T + i, 16 * cp + 4 * e + rho, part);
+  out[bi * 2048 + ((f >> 2) * 64 + lane) * 4 + (f & 3)] = v;
+}
+
+// Leaf pairs of a pass (tile, q: leaves (tile << K) + 2q + c) as two 16 x 16 FP32
+// blocks: in  M_c[a][p] = conj(W[j][p][a]),  out  M_c[p][a] = W[j][p][a];
+// value j of lane i + 16 e is [Re M_c, -Im M_c][i][(j / 4, 4 e + j % 4)].
+__global__ void k_pack_leaf16(const float2 *__restrict__ W, float *__restrict__ out, int64_t npairs,
+                              int K, int in) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= npairs * 1024) return;
+  const int64_t bi = t >> 10;
+  const int w = (int)(t & 1023);
+  const int c = w >> 9, pc = (w >> 8) & 1, lane = (w >> 2) & 63, jj = w & 3;
+  const int jv = pc * 4 + jj;  // value index 0..7
+  const int i = lane & 15, e = lane >> 4;
+  const int k = 4 * e + (jv & 3);
+  const int64_t tile = bi >> (K - 1), qq = bi & ((int64_t(1) << (K - 1)) - 1);
+  const int64_t leaf = (tile << K) + 2 * qq + c;
+  float2 m = in ? W[(leaf * kR + k) * kR + i] : W[(leaf * kR + i) * kR + k];
+  if (in) m.y = -m.y;
+  out[bi * 1024 + ((c * 2 + pc) * 64 + lane) * 4 + jj] = (jv >> 2) == 0 ? m.x : -m.y;
 }
 
 constexpr int kRowPad = 272;  // bytes per column of a staged 32-row chunk (256 + 16)
@@ -139,57 +176,6 @@ __global__ __launch_bounds__(256) void k_grad_leaf(const float2 *__restrict__ U,
   }
 }
 
-// y[j][a][n] = sum_p conj(W[j][p][a]) x[(j n0 + p) ld + n]: one thread per (leaf, column)
-__global__ void k_leaf_in16(const float2 *__restrict__ W, const float2 *__restrict__ x, int64_t ld,
-                            float2 *__restrict__ y, int64_t P, int64_t nrhs, int64_t npad, int cs) {
-  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (t >= P * npad) return;
-  const int64_t n = t % npad, j = t / npad;
-  float2 v[kR];
-#pragma unroll
-  for (int p = 0; p < kR; ++p)
-    v[p] = n < nrhs ? x[(j * kR + p) * ld + n] : make_float2(0.f, 0.f);
-  const float2 *w = W + j * kR * kR;
-  const int C = 1 << cs;
-  float2 *dst = y + ((n >> cs) * P + j) * 8 * (2 * C) + (n & (C - 1)) * 2;
-#pragma unroll
-  for (int a = 0; a < kR; ++a) {
-    float re = 0.f, im = 0.f;
-#pragma unroll
-    for (int p = 0; p < kR; ++p) {
-      const float2 c = w[p * kR + a];
-      re += c.x * v[p].x + c.y * v[p].y;
-      im += c.x * v[p].y - c.y * v[p].x;
-    }
-    dst[(a >> 1) * (2 * C) + (a & 1)] = make_float2(re, im);
-  }
-}
-
-// u[(i n0 + p) ld + n] = sum_a W[i][p][a] z[i][a][n]: one thread per (leaf, column)
-__global__ void k_leaf_out16(const float2 *__restrict__ W, const float2 *__restrict__ z,
-                             float2 *__restrict__ u, int64_t ld, int64_t P, int64_t nrhs, int cs) {
-  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (t >= P * nrhs) return;
-  const int64_t n = t % nrhs, i = t / nrhs;
-  const int C = 1 << cs;
-  const float2 *src = z + ((n >> cs) * P + i) * 8 * (2 * C) + (n & (C - 1)) * 2;
-  float2 v[kR];
-#pragma unroll
-  for (int a = 0; a < kR; ++a) v[a] = src[(a >> 1) * (2 * C) + (a & 1)];
-  const float2 *w = W + i * kR * kR;
-#pragma unroll
-  for (int p = 0; p < kR; ++p) {
-    float re = 0.f, im = 0.f;
-#pragma unroll
-    for (int a = 0; a < kR; ++a) {
-      const float2 c = w[p * kR + a];
-      re += c.x * v[a].x - c.y * v[a].y;
-      im += c.x * v[a].y + c.y * v[a].x;
-    }
-    u[(i * kR + p) * ld + n] = make_float2(re, im);
-  }
-}
-
 __global__ __launch_bounds__(256) void k_grad_level(const float2 *__restrict__ X,
                                                      const float2 *__restrict__ Y,
                                                      float2 *__restrict__ grad, int64_t nb,
@@ -247,28 +233,19 @@ hipError_t launch_grad_leaf_mfma(const bf_plan *p, const void *user, int64_t ld,
   return hipGetLastError();
 }
 
-hipError_t launch_leaf16(const bf_plan *p, const LevelOp &op, const void *in, void *out,
-                         int64_t nrhs, int64_t ld, hipStream_t s) {
+hipError_t launch_pack_pass(const PackPassArgs &a, void *out, hipStream_t s) {
   const int bs = 256;
-  const int cs = p->cs;
-  const int64_t npad = ((nrhs + (1 << cs) - 1) >> cs) << cs;
-  if (op.kind == LevelOp::kLeafIn)
-    hipLaunchKernelGGL(k_leaf_in16, dim3((unsigned)((p->P * npad + bs - 1) / bs)), dim3(bs), 0, s,
-                       (const float2 *)op.mat, (const float2 *)in, ld, (float2 *)out, p->P, nrhs,
-                       npad, cs);
-  else
-    hipLaunchKernelGGL(k_leaf_out16, dim3((unsigned)((p->P * nrhs + bs - 1) / bs)), dim3(bs), 0, s,
-                       (const float2 *)op.mat, (const float2 *)in, (float2 *)out, ld, p->P, nrhs,
-                       cs);
+  const int64_t total = (int64_t)a.K * a.ntiles * (int64_t(1) << (a.K - 1)) * 2048;
+  hipLaunchKernelGGL(k_pack_pass, dim3((unsigned)((total + bs - 1) / bs)), dim3(bs), 0, s, a, (float *)out);
   return hipGetLastError();
 }
 
-hipError_t launch_pack_level(const void *canon_level, void *out, int64_t nb, int64_t blo, bool tconj,
-                             hipStream_t s) {
+hipError_t launch_pack_leaf16(const void *canon_leaf, void *out, int64_t npairs, int K, bool in,
+                              hipStream_t s) {
   const int bs = 256;
-  const int64_t total = nb * 64 * 32;
-  hipLaunchKernelGGL(k_pack_level, dim3((unsigned)((total + bs - 1) / bs)), dim3(bs), 0, s,
-                     (const float2 *)canon_level, (float *)out, nb, blo, tconj ? 1 : 0);
+  const int64_t total = npairs * 1024;
+  hipLaunchKernelGGL(k_pack_leaf16, dim3((unsigned)((total + bs - 1) / bs)), dim3(bs), 0, s,
+                     (const float2 *)canon_leaf, (float *)out, npairs, K, in ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -387,6 +387,7 @@ FusedArgs pass_args(const bf_plan *p, const FusedPass *fp, const void *in, void 
   a.in_kind = fp->in_kind;
   a.out_kind = fp->out_kind;
   a.ngroups = 1;
+  for (auto &q : a.lvl) q = nullptr;
   a.log_m = 0;
   while ((int64_t(1) << a.log_m) < a.m) ++a.log_m;
   return a;
@@ -491,53 +492,106 @@ hipError_t fused_run(bf_plan *p, bool adjoint, const void *g, void *u, int64_t n
   return hipSuccess;
 }
 
-// One-level FP32 passes (16-column geometry) for every butterfly op of the
-// forward and adjoint op lists; their blocks are packed on the device from the
-// canonical factors the handle already holds.
+// FP32 passes of the backward pass: the pass split of the apply, 16-column
+// geometry, blocks packed on the device from the canonical factors the handle
+// holds.  The forward list has no leaf-out blocks: the backward pass needs the
+// state before U^L, not u.
 bf_status fused_build_backward(bf_plan *p, hipStream_t s) {
-  auto build = [&](const std::vector<LevelOp> &ops, std::vector<FusedPass *> &out) -> bf_status {
-    out.assign(ops.size(), nullptr);
-    for (size_t t = 0; t < ops.size(); ++t) {
-      const LevelOp &op = ops[t];
-      if (op.kind != LevelOp::kButterfly) continue;
-      FusedPass *fp = new FusedPass();
-      out[t] = fp;
-      fp->K = 1;
-      fp->cols = 16;
-      fp->log_slo = p->L - op.level - 1;
-      fp->mode_si = op.mode == kStridedIn ? 1 : 0;
-      fp->in_kind = kInAct;
-      fp->out_kind = kOutAct;
-      fp->ntiles = op.nb;
-      fp->name = op.name + "_pass";
-      void *d = nullptr;
-      const size_t bytes = (size_t)op.nb * kBlockBytes;
-      hipError_t e = hipMalloc(&d, bytes);
-      if (e != hipSuccess) {
-        (void)hipGetLastError();
-        p->err = std::string("backward pack allocation: ") + hipGetErrorString(e);
-        return BF_ERR_ALLOC;
-      }
-      fp->owned.push_back(d);
-      fp->fac = d;
-      e = launch_pack_level(op.mat, d, op.nb, op.blo, op.tconj, s);
-      if (e != hipSuccess) {
-        p->err = std::string("backward pack: ") + hipGetErrorString(e);
-        return BF_ERR_HIP;
-      }
+  const int L = p->L, h = p->h;
+  const std::vector<int> ks = split_levels(h, 4);
+  // middle weights (S, S^T) as the apply passes hold them
+  const float *Sm[2] = {nullptr, nullptr};
+  for (int dir = 0; dir < 2; ++dir)
+    for (const FusedPass *q : dir ? p->adj_passes : p->fwd_passes)
+      if (q->in_kind == kInMiddle) Sm[dir] = q->Sm;
+  auto alloc = [&](FusedPass *fp, size_t bytes, void **d) -> bf_status {
+    hipError_t e = hipMalloc(d, bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      p->err = std::string("backward pack allocation: ") + hipGetErrorString(e);
+      return BF_ERR_ALLOC;
     }
+    fp->owned.push_back(*d);
     return BF_OK;
   };
-  bf_status st = build(p->fwd_ops, p->bwd_fwd);
-  if (st == BF_OK) st = build(p->adj_ops, p->bwd_adj);
-  if (st == BF_OK) p->bwd_ready = true;
-  return st;
+  for (int dir = 0; dir < 2; ++dir) {
+    const bool adj = dir == 1;
+    const auto &ops = adj ? p->adj_ops : p->fwd_ops;
+    auto &list = adj ? p->bwd_adj : p->bwd_fwd;
+    int t_first = 1;  // op index of the pass's first butterfly level
+    for (int sd = 0; sd < 2; ++sd) {
+      int l_edge = sd == 0 ? L : h;
+      for (size_t t = 0; t < ks.size(); ++t) {
+        const int K = sd == 0 ? ks[t] : ks[ks.size() - 1 - t];
+        FusedPass *fp = new FusedPass();
+        list.push_back(fp);
+        const int l_hi = sd == 0 ? l_edge : l_edge + K;
+        const PassSide side = sd == 0 ? (adj ? kGadj : kHfwd) : (adj ? kHadj : kGfwd);
+        fp->K = K;
+        fp->cols = 16;
+        fp->split = K >= 4;
+        fp->log_slo = L - l_hi;
+        fp->mode_si = (side == kHfwd || side == kGadj) ? 1 : 0;
+        fp->in_kind = t == 0 ? (sd == 0 ? kInUser : kInMiddle) : kInAct;
+        fp->out_kind = (adj && sd == 1 && t + 1 == ks.size()) ? kOutUser : kOutAct;
+        fp->ntiles = int64_t(1) << (L - K);
+        fp->Sm = (sd == 1 && t == 0) ? Sm[dir] : nullptr;
+        static const char *side_name[] = {"H_fwd", "G_fwd", "G_adj", "H_adj"};
+        fp->name = std::string("bwd_") + side_name[side] + "_l" + std::to_string(l_hi) + "_" +
+                   std::to_string(l_hi - K);
+        if (sd == 1 && t == 0) ++t_first;  // the middle op
+        PackPassArgs pa;
+        pa.K = K;
+        pa.log_slo = fp->log_slo;
+        pa.mode_si = fp->mode_si;
+        pa.ntiles = fp->ntiles;
+        for (int d = 0; d < K; ++d) {
+          const LevelOp &op = ops[t_first + d];
+          int lb = 0;
+          while ((int64_t(1) << lb) < op.blo) ++lb;
+          pa.dep[d].Fb = op.mat;
+          pa.dep[d].log_blo = lb;
+          pa.dep[d].tconj = op.tconj ? 1 : 0;
+          pa.dep[d].contig = op.mode == kContigIn ? 1 : 0;
+        }
+        const int64_t NB = int64_t(1) << (K - 1);
+        void *d = nullptr;
+        bf_status st = alloc(fp, (size_t)(K * fp->ntiles * NB) * kBlockBytes, &d);
+        if (st != BF_OK) return st;
+        fp->fac = d;
+        hipError_t e = launch_pack_pass(pa, d, s);
+        if (e == hipSuccess && (fp->in_kind == kInUser || fp->out_kind == kOutUser)) {
+          const bool in = fp->in_kind == kInUser;
+          const LevelOp &lop = in ? ops.front() : ops.back();
+          if ((st = alloc(fp, (size_t)(fp->ntiles * NB) * (kBlockBytes / 2), &d)) != BF_OK) return st;
+          fp->leaf = d;
+          e = launch_pack_leaf16(lop.mat, d, fp->ntiles * NB, K, in, s);
+        }
+        if (e != hipSuccess) {
+          p->err = std::string("backward pack: ") + hipGetErrorString(e);
+          return BF_ERR_HIP;
+        }
+        t_first += K;
+        l_edge = sd == 0 ? l_edge - K : l_edge + K;
+      }
+    }
+  }
+  p->bwd_ready = true;
+  return BF_OK;
 }
 
-hipError_t fused_run_level(const bf_plan *p, const FusedPass *fp, const void *in, void *out,
-                           int64_t nrhs, hipStream_t s) {
-  FusedArgs a = pass_args(p, fp, in, out, nrhs, 0);
-  return launch_prec<kF32>(a, fp->cols, fp->K, false, false, false, s);
+PassShape fused_pass_shape(const FusedPass *fp) {
+  return PassShape{fp->K, fp->in_kind == kInUser, fp->in_kind == kInMiddle, fp->out_kind == kOutUser,
+                   &fp->name};
+}
+
+hipError_t fused_run_pass(const bf_plan *p, const FusedPass *fp, const void *in, void *out,
+                          void *const *lvl, int64_t nrhs, int64_t ld, hipStream_t s) {
+  FusedArgs a = pass_args(p, fp, in, out, nrhs, ld);
+  if (lvl)
+    for (int d = 0; d <= fp->K; ++d) a.lvl[d] = lvl[d];
+  const bool li = fp->in_kind == kInUser, lo = fp->out_kind == kOutUser;
+  return launch_prec<kF32>(a, fp->cols, fp->K, li, lo, fp->split, s);
 }
 
 void fused_free(FusedPass *fp) {

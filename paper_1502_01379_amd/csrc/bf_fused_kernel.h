@@ -72,7 +72,25 @@ struct FusedArgs {
   const float *Sm;      // middle weights in natural slot order (kInMiddle)
   int64_t ld, nrhs, nchunks, nslots, ntiles, m;
   int log_slo, mode_si, in_kind, out_kind, ngroups, log_m;
+  // optional per-depth copies of the state in the activation layout (used by the
+  // backward pass): lvl[0] after the leaf blocks or the middle weights, lvl[d]
+  // after d levels (d < K, or d = K before the leaf-out blocks); nullptr: none
+  void *lvl[5];
 };
+
+// Slot (in the global slot order of the level-by-level chain) of tile-local slot
+// q after d of the pass's K levels.  A level that reads strided slots moves the
+// paired bit to the bottom of the low bits; one that reads contiguous slots moves
+// the bottom bit up: after d levels the first d output bits sit next to the tile's
+// lo bits and the K - d unprocessed input bits keep their places.
+template <int K>
+__device__ __forceinline__ int64_t slot_at_depth(const FusedArgs &a, int64_t base, int64_t lo, int64_t q,
+                                                 int d) {
+  const int64_t dm = (int64_t(1) << d) - 1;
+  if (a.mode_si)
+    return base + ((q >> d) << (d + a.log_slo)) + (lo << d) + (q & dm);
+  return base + ((q & dm) << (K - d + a.log_slo)) + (lo << (K - d)) + (q >> d);
+}
 
 struct BlockA {
   u32x4 v[8];  // this lane's 128 bytes of one packed block
@@ -620,8 +638,25 @@ void k_fused_pass(FusedArgs a) {
     });
   };
 
+  // copy of the state after d levels into a.lvl[d] (activation layout)
+  auto store_depth = [&](int d) {
+    f32x4 *dst = static_cast<f32x4 *>(a.lvl[d]);
+    if (!dst) return;
+    static_for<NS>([&](auto Q) {
+      constexpr int q = Q;
+      const int64_t slot = slot_at_depth<K>(a, base, lo, q, d);
+      f32x4 *p = dst + ((chunk * a.nslots + slot) * 8) * COLS + n;
+      static_for<NR / 2>([&](auto J) {
+        constexpr int j = J;
+        const f32x4 v = {st[q][2 * j], st[q][NR + 2 * j], st[q][2 * j + 1], st[q][NR + 2 * j + 1]};
+        __builtin_nontemporal_store(v, p + G::pair(e, j) * COLS);
+      });
+    });
+  };
+
   // ---- leaf blocks applied to slot pairs before the first level
   if constexpr (LI) pair_group(std::integral_constant<int, 0>{});
+  if (LI || a.in_kind == kInMiddle) store_depth(0);
 
   // ---- K butterfly levels
   static_for<K>([&](auto D) {
@@ -639,6 +674,7 @@ void k_fused_pass(FusedArgs a) {
     static_for<NS>([&](auto Q) {
       static_for<SW>([&](auto J) { st[Q][J] = nx[Q][J]; });
     });
+    if (d + 1 < K || LO) store_depth(d + 1);
   });
 
   // ---- leaf blocks after the last level
@@ -832,7 +868,24 @@ void k_fused_pass_x2(FusedArgs a) {
     });
   };
 
+  // copy of this half's state after d levels into a.lvl[d] (activation layout)
+  auto store_depth = [&](int d) {
+    f32x4 *dst = static_cast<f32x4 *>(a.lvl[d]);
+    if (!dst || !active) return;
+    static_for<HS>([&](auto J) {
+      constexpr int j = J;
+      const int64_t slot = slot_at_depth<K>(a, base, lo, qh + j, d);
+      f32x4 *p = dst + ((chunk * a.nslots + slot) * 8) * 16 + n;
+      static_for<NR / 2>([&](auto JJ) {
+        constexpr int jj = JJ;
+        const f32x4 v = {st[j][2 * jj], st[j][NR + 2 * jj], st[j][2 * jj + 1], st[j][NR + 2 * jj + 1]};
+        __builtin_nontemporal_store(v, p + G::pair(e, jj) * 16);
+      });
+    });
+  };
+
   if constexpr (LI) pair_group(std::integral_constant<int, 0>{});
+  if (LI || a.in_kind == kInMiddle) store_depth(0);
 
   // ---- levels 0 .. K-2 inside the half
   static_for<K - 1>([&](auto D) {
@@ -850,6 +903,7 @@ void k_fused_pass_x2(FusedArgs a) {
     static_for<HS>([&](auto Q) {
       static_for<SW>([&](auto JJ) { st[Q][JJ] = nx[Q][JJ]; });
     });
+    store_depth(d + 1);
   });
 
   // ---- swap halves through the swap region: kp[k] is the operand this
@@ -899,6 +953,7 @@ void k_fused_pass_x2(FusedArgs a) {
     });
     step(std::integral_constant<int, gl>{}, BW, x0, x1, st[2 * k], st[2 * k + 1]);
   });
+  if constexpr (LO) store_depth(K);
 
   if constexpr (LO) pair_group(std::integral_constant<int, (LI ? 1 : 0) + K>{});
 

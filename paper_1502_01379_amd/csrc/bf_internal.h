@@ -46,6 +46,19 @@ struct LevelOp {
 
 struct FusedPass;  // fused MFMA pass description (bf_fused.hip)
 
+// Device packing of the blocks of one K-level FP32 pass from canonical factors.
+struct PackDepth {
+  const void *Fb = nullptr;  // canonical blocks of the level at this depth
+  int log_blo = 0;           // log2 of the level's blo
+  int tconj = 0;             // conjugate-transposed blocks
+  int contig = 0;            // the level reads contiguous slots
+};
+struct PackPassArgs {
+  PackDepth dep[4];
+  int K = 0, log_slo = 0, mode_si = 0;
+  int64_t ntiles = 0;
+};
+
 struct ProfRec {
   std::string name;
   hipEvent_t start, stop;
@@ -67,8 +80,8 @@ struct bf_plan {
   std::vector<bfly::LevelOp> fwd_ops, adj_ops;
   // fused path
   std::vector<bfly::FusedPass *> fwd_passes, adj_passes;
-  // one-level FP32 fused passes used by the backward pass, built on first use and
-  // indexed by the position of the op in fwd_ops / adj_ops (nullptr: not a butterfly)
+  // FP32 fused passes of the backward pass (same pass split as the apply; the
+  // forward list stops before the leaf-out blocks), built on first use
   std::vector<bfly::FusedPass *> bwd_fwd, bwd_adj;
   bool bwd_ready = false;
   // middle weights, FP32 or FP64 by precision: S[i][j][k] and its transpose
@@ -102,22 +115,31 @@ hipError_t launch_middle_grad(const bf_plan *p, const void *dz, const void *y, v
                               int64_t nrhs, hipStream_t s);
 
 // Backward helpers for fused-path handles (bf_bwd.hip)
-hipError_t launch_pack_level(const void *canon_level, void *out, int64_t nb, int64_t blo, bool tconj,
-                             hipStream_t s);
+hipError_t launch_pack_pass(const PackPassArgs &a, void *out, hipStream_t s);
+hipError_t launch_pack_leaf16(const void *canon_leaf, void *out, int64_t npairs, int K, bool in,
+                              hipStream_t s);
 hipError_t launch_grad_level_mfma(const bf_plan *p, const LevelOp &op, const void *X, const void *Y,
                                   void *grad, int64_t nrhs, hipStream_t s);
 hipError_t launch_grad_leaf_mfma(const bf_plan *p, const void *user, int64_t ld, const void *act,
                                  void *grad, int64_t nrhs, hipStream_t s);
-// leaf-in / leaf-out ops for leaf 16, rank 16 in FP32, one thread per (leaf, column)
-hipError_t launch_leaf16(const bf_plan *p, const LevelOp &op, const void *in, void *out,
-                         int64_t nrhs, int64_t ld, hipStream_t s);
 
 // Fused path (bf_fused.hip)
 bool fused_supported(const bf_shape &sh, bf_precision prec);
-// one-level FP32 passes for the backward pass (blocks packed on the device)
+// FP32 passes of the backward pass (blocks packed on the device from the
+// canonical factors)
 bf_status fused_build_backward(bf_plan *p, hipStream_t s);
-hipError_t fused_run_level(const bf_plan *p, const FusedPass *fp, const void *in, void *out,
-                           int64_t nrhs, hipStream_t s);
+// Shape of one pass of a pass list: K levels, leaf blocks in front (li), the
+// middle weights in front (mid), leaf blocks behind (lo), and its name.
+struct PassShape {
+  int K;
+  bool li, mid, lo;
+  const std::string *name;
+};
+PassShape fused_pass_shape(const FusedPass *fp);
+// One pass with optional per-depth copies of the state: lvl[d] (d = 0 .. K,
+// nullptr to skip) receives the state after d levels in the activation layout.
+hipError_t fused_run_pass(const bf_plan *p, const FusedPass *fp, const void *in, void *out,
+                          void *const *lvl, int64_t nrhs, int64_t ld, hipStream_t s);
 bf_status fused_build(bf_plan *p, const bf_factors_host *f);
 hipError_t fused_run(bf_plan *p, bool adjoint, const void *g, void *u, int64_t nrhs, int64_t ld,
                      void *buf0, void *buf1, hipStream_t s);

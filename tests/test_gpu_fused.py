@@ -161,6 +161,51 @@ def test_backward_on_fused_handle(dev, fio4096, prec):
     assert oracle.rel_err(grads["S"].cpu().numpy(), ref["S"]) < 1e-4
 
 
+def _flat(d):
+    return [d["VL"], d["UL"], d["S"], *d["H"], *d["G"]]
+
+
+@pytest.mark.parametrize("L", [2, 4, 6, 8, 10, 14])
+@pytest.mark.parametrize("prec", ["f32", "bf16x3"])
+def test_fused_backward_tree_depths(dev, L, prec):
+    # backward passes of one to four levels, one or two passes per side; every
+    # gradient against the oracle, and recomputing the states inside the passes
+    # gives the same bits as keeping them
+    from paper_1502_01379_amd import BF_BWD_STORE_ALL
+    f = synthetic_factors(2, 16, L, 16, seed=80 + L)
+    N = 16 * 2 ** L
+    nrhs = 19 if L < 14 else 5
+    g = complex_gaussian((N, nrhs), 81 + L)
+    gu = complex_gaussian((N, nrhs), 82 + L)
+    ref = oracle.bf_grad(f, g, gu)
+    h = _handle(f, prec)
+    grad_g, grads = h.backward(_dev(g, dev), _dev(gu, dev))
+    assert oracle.rel_err(grad_g.cpu().numpy(), ref["g"]) < 1e-5
+    for a, b in zip(_flat(grads), _flat(ref)):
+        assert oracle.rel_err(a.cpu().numpy(), b) < 1e-5
+    grad_g2, grads2 = h.backward(_dev(g, dev), _dev(gu, dev), flags=BF_BWD_STORE_ALL)
+    assert torch.equal(grad_g, grad_g2)
+    for a, b in zip(_flat(grads), _flat(grads2)):
+        assert torch.equal(a, b)
+
+
+def test_fused_backward_without_grad_g(dev):
+    # factor gradients only (the leaf-out result goes to scratch), then grad_g only
+    f = synthetic_factors(2, 16, 6, 16, seed=90)
+    N = 1024
+    g = complex_gaussian((N, 33), 91)
+    gu = complex_gaussian((N, 33), 92)
+    ref = oracle.bf_grad(f, g, gu)
+    h = _handle(f, "f32")
+    none_g, grads = h.backward(_dev(g, dev), _dev(gu, dev), need_grad_g=False)
+    assert none_g is None
+    for a, b in zip(_flat(grads), _flat(ref)):
+        assert oracle.rel_err(a.cpu().numpy(), b) < 1e-5
+    grad_g, empty = h.backward(_dev(g, dev), _dev(gu, dev), factor_grads=False)
+    assert empty == {}
+    assert oracle.rel_err(grad_g.cpu().numpy(), ref["g"]) < 1e-5
+
+
 def test_full_size_2_20_256_rhs(dev):
     # N = 2^20, leaf 16, r = 16 (L = 16), 256 right-hand sides; synthetic factors of
     # the real shapes; every row of three sampled columns is compared with the oracle
