@@ -134,9 +134,15 @@ bf_status bf_apply_adjoint(bf_handle h, const void *w, void *v, int64_t nrhs, in
  *   forward-applied blocks B (G, U^L):      grad_B = sum_n d_out x_in^*
  *   adjoint-applied blocks W (H, V^L):      grad_W = sum_n x_in d_out^*
  *   middle weights (real):                  grad_S = sum_n Re(d_z conj(y))
- * Forward activations are recomputed level by level inside the call (flags =
- * BF_BWD_RECOMPUTE, the default 0) or kept for every level of the tree
- * (BF_BWD_STORE_ALL, more workspace).  Gradients are overwritten, not added to. */
+ * The forward states of the chain are needed level by level.  With flags =
+ * BF_BWD_RECOMPUTE (the default 0) only some of them are kept (the pass
+ * boundaries on the fused path, every fourth level otherwise) and the others
+ * are recomputed inside the call; BF_BWD_STORE_ALL keeps all 2h + 2 of them
+ * (more workspace, less work).  Both modes give identical results.  On the fused
+ * path the backward pass computes in FP32 for every precision.  The workspace
+ * (owned by the handle, grown on demand) is about (2h + 8) activation arrays
+ * with BF_BWD_STORE_ALL and 15 without, each P r nrhs complex values.
+ * Gradients are overwritten, not added to. */
 #define BF_BWD_RECOMPUTE 0u
 #define BF_BWD_STORE_ALL 1u
 bf_status bf_backward(bf_handle h, const void *g, const void *grad_u, void *grad_g,
