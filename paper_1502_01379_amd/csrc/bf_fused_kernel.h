@@ -721,6 +721,12 @@ void k_fused_pass(FusedArgs a) {
 // LDS region of its own.  Workgroups hold 1, 2 or 4 column chunks (2, 4 or 8
 // wavefronts); a wavefront pair past the last chunk stays resident, loading and
 // storing nothing, and takes its share of the block copies.
+#ifndef BF_SPLIT_MAX_PAIRS
+#define BF_SPLIT_MAX_PAIRS 4
+#endif
+#ifndef BF_SPLIT_SWAP_KB
+#define BF_SPLIT_SWAP_KB 16
+#endif
 template <int K>
 struct SplitTraits {
   static constexpr int kHS = 1 << (K - 1);  // slots per wavefront
@@ -728,15 +734,15 @@ struct SplitTraits {
   static constexpr int kPB = kWB < 2 ? kWB : 2;  // blocks per wavefront per stage
   static constexpr int kHB = 2 * kPB;            // blocks per stage
   static constexpr int kNPART = kWB / kPB;       // stages per block group
-  static constexpr int kMaxPairs = 4;            // column chunks per workgroup
-  static constexpr int kSwapBytes = 16 * 1024;
+  static constexpr int kMaxPairs = BF_SPLIT_MAX_PAIRS;  // column chunks per workgroup
+  static constexpr int kSwapBytes = BF_SPLIT_SWAP_KB * 1024;
   static constexpr int kSR = kSwapBytes / (2 * kMaxPairs * 2048);  // slots per swap round
   static constexpr int kRounds = (kWB + kSR - 1) / kSR;
   static constexpr int kLdsBytes = 2 * kHB * kBlockBytes + kSwapBytes;
 };
 
 template <int K, int PREC, bool LI, bool LO>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ __launch_bounds__(BF_SPLIT_MAX_PAIRS * 128) __attribute__((amdgpu_waves_per_eu(4)))
 void k_fused_pass_x2(FusedArgs a) {
   using T = SplitTraits<K>;
   using G = Geo<16>;
@@ -750,7 +756,7 @@ void k_fused_pass_x2(FusedArgs a) {
   const int n = lane & 15, e = lane >> 4;
   int64_t tile, group;
   tile_of_block(a, tile, group);
-  const int W = (int)(blockDim.x >> 6);  // 2, 4 or 8 wavefronts
+  const int W = (int)(blockDim.x >> 6);  // 2, 4, 8 (or 16) wavefronts
   const int64_t chunk = group * (W >> 1) + (wave >> 1);
   const bool active = chunk < a.nchunks;
   const int64_t slo = int64_t(1) << a.log_slo;
@@ -1006,7 +1012,8 @@ hipError_t launch_prec(FusedArgs a, int cols, int K, bool leaf_in, bool leaf_out
 
 #define BF_FUSED_LAUNCH_X2(KK, PREC, LI, LO)                                                  \
   do {                                                                                        \
-    const int64_t w = a.nchunks >= 4 ? 4 : a.nchunks >= 2 ? 2 : 1;                            \
+    const int64_t w = a.nchunks >= BF_SPLIT_MAX_PAIRS ? BF_SPLIT_MAX_PAIRS                  \
+                      : a.nchunks >= 4 ? 4 : a.nchunks >= 2 ? 2 : 1;                            \
     a.ngroups = (int)((a.nchunks + w - 1) / w);                                               \
     hipLaunchKernelGGL((k_fused_pass_x2<KK, PREC, LI, LO>),                                   \
                        dim3((unsigned)(a.ntiles * a.ngroups)), dim3((unsigned)(w * 128)), 0, s, \
