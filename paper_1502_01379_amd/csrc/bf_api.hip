@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -360,6 +361,25 @@ bf_status bf_create_from_factors(const bf_shape *shape, const bf_factors_host *f
     if (fused) {
       p->path = 1;
       st = bfly::fused_build(p, f);
+    } else if (prec == BF_PREC_F32 && bfly::level_mfma_supported(p->R, p->r) &&
+               !std::getenv("BF_DISABLE_LEVEL_MFMA")) {
+      // butterfly levels on the matrix cores: blocks packed on the device
+      for (auto *ops : {&p->fwd_ops, &p->adj_ops})
+        for (LevelOp &op : *ops) {
+          if (op.kind != LevelOp::kButterfly || st != BF_OK) continue;
+          void *d = nullptr;
+          const size_t bytes = (size_t)op.nb * (size_t)(p->R * p->r) * (size_t)(2 * p->R * p->r) * 4;
+          hipError_t e = hipMalloc(&d, bytes);
+          if (e != hipSuccess) {
+            (void)hipGetLastError();
+            st = fail(p, BF_ERR_ALLOC, std::string("level block allocation: ") + hipGetErrorString(e));
+            break;
+          }
+          p->allocs.push_back(d);
+          if ((e = bfly::launch_pack_level_mfma(op, p->R, p->r, d, stream)) != hipSuccess)
+            st = fail(p, BF_ERR_HIP, std::string("level block packing: ") + hipGetErrorString(e));
+          op.packed = d;
+        }
     }
   }
   if (st == BF_OK) {
@@ -517,7 +537,7 @@ bf_status backward_fused(bf_plan *p, const void *g, const void *grad_u, void *gr
       if (t == 0) {
         if (grads && grads->VL) BWD_LAUNCH("grad_VL", bfly::launch_grad_leaf_mfma(p, g, ld, dout, grads->VL, nrhs, s));
       } else if (t == h + 1) {
-        if (grads && grads->S) BWD_LAUNCH("grad_S", bfly::launch_middle_grad(p, dout, aptr[h], grads->S, nrhs, s));
+        if (grads && grads->S) BWD_LAUNCH("grad_S", bfly::launch_grad_middle(p, dout, aptr[h], grads->S, nrhs, s));
       } else {
         const bfly::LevelOp &op = F[t];
         const bool is_g = t > h + 1;

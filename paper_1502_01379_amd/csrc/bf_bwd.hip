@@ -5,6 +5,7 @@
 //    in the per-lane A-operand order of the 16-column block products, so the
 //    backward pass runs the same fused passes as the apply in FP32.
 //  * k_grad_leaf: the gradient of the leaf blocks (two leaves per wavefront).
+//  * k_grad_middle: the gradient of the middle weights (one wavefront per slot).
 //  * k_grad_level: the gradient of every block of one level,
 //        grad[2 hi + cx][lo][rx][cy r + ry] = sum_n X[strided(b,cx)][rx][n] conj(Y[contig(b,cy)][ry][n]),
 //    (grad_B = sum_n d_out x_in^* for G levels with X = d_out, Y = x_in;
@@ -95,11 +96,16 @@ __global__ void k_pack_leaf16(const float2 *__restrict__ W, float *__restrict__ 
 
 constexpr int kRowPad = 272;  // bytes per column of a staged 32-row chunk (256 + 16)
 
-// Stage rows (2 slots x 16 rows) x 16 columns [n0, n0 + 16) of one activation
-// operand into LDS as [column][row] complex, row stride kRowPad bytes.
-__device__ __forceinline__ void stage_chunk(const float2 *__restrict__ act, int64_t nslots,
-                                            int64_t s0, int64_t s1, int64_t n0, int cs,
-                                            char *lds, int lane) {
+// Rows (2 slots x 16 rows) x 16 columns [n0, n0 + 16) of one activation operand:
+// this lane's four 16-byte pieces (two complex values of one column each) are
+// loaded into registers, then written to LDS as [column][row] complex with row
+// stride kRowPad bytes.
+struct Chunk {
+  f32x4 v[4];
+};
+__device__ __forceinline__ void load_chunk(const float2 *__restrict__ act, int64_t nslots,
+                                           int64_t s0, int64_t s1, int64_t n0, int cs, int lane,
+                                           Chunk &ch) {
   const int C = 1 << cs;
   const int64_t chunk = n0 >> cs;
   const int nb = (int)(n0 & (C - 1));
@@ -110,11 +116,24 @@ __device__ __forceinline__ void stage_chunk(const float2 *__restrict__ act, int6
     const int p = (piece >> 4) & 7;           // row pair
     const int n = piece & 15;                 // column within the 16
     const int64_t slot = c ? s1 : s0;
-    const f32x4 *src = reinterpret_cast<const f32x4 *>(
-        act + ((chunk * nslots + slot) * 8 + p) * (2 * C) + (int64_t)(nb + n) * 2);
-    const f32x4 val = *src;
-    *reinterpret_cast<f32x4 *>(lds + n * kRowPad + (c * 16 + 2 * p) * 8) = val;
+    ch.v[v] = *reinterpret_cast<const f32x4 *>(act + ((chunk * nslots + slot) * 8 + p) * (2 * C) +
+                                               (int64_t)(nb + n) * 2);
   }
+}
+__device__ __forceinline__ void store_chunk(const Chunk &ch, char *lds, int lane) {
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int piece = v * 64 + lane;
+    const int c = piece >> 7, p = (piece >> 4) & 7, n = piece & 15;
+    *reinterpret_cast<f32x4 *>(lds + n * kRowPad + (c * 16 + 2 * p) * 8) = ch.v[v];
+  }
+}
+__device__ __forceinline__ void stage_chunk(const float2 *__restrict__ act, int64_t nslots,
+                                            int64_t s0, int64_t s1, int64_t n0, int cs,
+                                            char *lds, int lane) {
+  Chunk ch;
+  load_chunk(act, nslots, s0, s1, n0, cs, lane, ch);
+  store_chunk(ch, lds, lane);
 }
 
 // Stage rows (2 leaves x 16 points) x 16 columns [n0, n0 + 16) of a user vector
@@ -192,10 +211,18 @@ __global__ __launch_bounds__(256) void k_grad_level(const float2 *__restrict__ X
   const int i = lane & 31, eta = lane >> 5;
   floatx16 dre = {}, dim = {};
   const int64_t npad = ((nrhs + 15) >> 4) << 4;
+  // the next chunk's loads are in flight while the current one is contracted
+  Chunk cx, cy;
+  load_chunk(X, nslots, sx0, sx1, 0, cs, lane, cx);
+  load_chunk(Y, nslots, sy0, sy1, 0, cs, lane, cy);
   for (int64_t n0 = 0; n0 < npad; n0 += 16) {
-    stage_chunk(X, nslots, sx0, sx1, n0, cs, lx, lane);
-    stage_chunk(Y, nslots, sy0, sy1, n0, cs, ly, lane);
-    __builtin_amdgcn_s_waitcnt(0);
+    store_chunk(cx, lx, lane);
+    store_chunk(cy, ly, lane);
+    if (n0 + 16 < npad) {
+      load_chunk(X, nslots, sx0, sx1, n0 + 16, cs, lane, cx);
+      load_chunk(Y, nslots, sy0, sy1, n0 + 16, cs, lane, cy);
+    }
+    __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): this wavefront's LDS writes are done
     __builtin_amdgcn_wave_barrier();
 #pragma unroll
     for (int s = 0; s < 8; ++s) {
@@ -222,7 +249,57 @@ __global__ __launch_bounds__(256) void k_grad_level(const float2 *__restrict__ X
   }
 }
 
+// grad_S[i][j][k] = Re sum_n dz[(i m + j)][k][n] conj(y[(j m + i)][k][n]) (the
+// middle weights scale slot i m + j by S[i][j] after the block transpose).  One
+// wavefront per slot s = i m + j: per 16-column chunk the two slots are 2 KB
+// each, read as 128 pieces of (rows 2p, 2p + 1; column n); lane l takes pieces
+// l and l + 64 (pairs p = l / 16 and 4 + l / 16), and the 16 columns are summed
+// across lanes at the end.
+__global__ __launch_bounds__(256) void k_grad_middle(const f32x4 *__restrict__ dz,
+                                                      const f32x4 *__restrict__ y,
+                                                      float *__restrict__ grad, int64_t nslots,
+                                                      int64_t nchunks, int log_m) {
+  const int lane = threadIdx.x & 63;
+  const int64_t s = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (s >= nslots) return;
+  const int64_t m = int64_t(1) << log_m;
+  const int64_t tr = ((s & (m - 1)) << log_m) | (s >> log_m);
+  float acc[4] = {0.f, 0.f, 0.f, 0.f};  // rows 2p, 2p + 1 for p = lane / 16 and 4 + lane / 16
+  for (int64_t c = 0; c < nchunks; ++c) {
+    const f32x4 *a = dz + (c * nslots + s) * 128 + lane;
+    const f32x4 *b = y + (c * nslots + tr) * 128 + lane;
+#pragma unroll
+    for (int v = 0; v < 2; ++v) {
+      const f32x4 x = a[v * 64], w = b[v * 64];
+      acc[2 * v] += x.x * w.x + x.y * w.y;
+      acc[2 * v + 1] += x.z * w.z + x.w * w.w;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int off = 1; off < 16; off <<= 1) acc[q] += __shfl_xor(acc[q], off);
+  if ((lane & 15) == 0) {
+    const int p = lane >> 4;
+    float *g = grad + s * kR;
+    g[2 * p] = acc[0];
+    g[2 * p + 1] = acc[1];
+    g[8 + 2 * p] = acc[2];
+    g[8 + 2 * p + 1] = acc[3];
+  }
+}
+
 }  // namespace
+
+hipError_t launch_grad_middle(const bf_plan *p, const void *dz, const void *y, void *grad,
+                              int64_t nrhs, hipStream_t s) {
+  int log_m = 0;
+  while ((int64_t(1) << log_m) < p->m) ++log_m;
+  const int64_t nchunks = (nrhs + 15) / 16;
+  hipLaunchKernelGGL(k_grad_middle, dim3((unsigned)((p->P + 3) / 4)), dim3(256), 0, s,
+                     (const f32x4 *)dz, (const f32x4 *)y, (float *)grad, p->P, nchunks, log_m);
+  return hipGetLastError();
+}
 
 hipError_t launch_grad_leaf_mfma(const bf_plan *p, const void *user, int64_t ld, const void *act,
                                  void *grad, int64_t nrhs, hipStream_t s) {

@@ -40,6 +40,7 @@ struct LevelOp {
   int64_t blo = 0;   // see SlotMode
   bool tconj = false; // butterfly: conjugate-transposed blocks; middle: transposed S
   const void *mat = nullptr;  // canonical factor array of this op (device)
+  const void *packed = nullptr;  // butterfly, FP32: blocks packed for k_level_mfma (or nullptr)
   int level = -1;             // butterfly: tree level l of the factor
   std::string name;
 };
@@ -114,12 +115,21 @@ hipError_t launch_leaf_grad(const bf_plan *p, const void *user, int64_t ld, cons
 hipError_t launch_middle_grad(const bf_plan *p, const void *dz, const void *y, void *grad,
                               int64_t nrhs, hipStream_t s);
 
+// Per-level butterflies on the matrix cores (bf_level.hip): FP32, R r in {32, 64, 128}, r even
+bool level_mfma_supported(int R, int r);
+hipError_t launch_pack_level_mfma(const LevelOp &op, int R, int r, void *out, hipStream_t s);
+hipError_t launch_level_mfma(const bf_plan *p, const LevelOp &op, const void *in, void *out,
+                             int64_t nrhs, hipStream_t s);
+
 // Backward helpers for fused-path handles (bf_bwd.hip)
 hipError_t launch_pack_pass(const PackPassArgs &a, void *out, hipStream_t s);
 hipError_t launch_pack_leaf16(const void *canon_leaf, void *out, int64_t npairs, int K, bool in,
                               hipStream_t s);
 hipError_t launch_grad_level_mfma(const bf_plan *p, const LevelOp &op, const void *X, const void *Y,
                                   void *grad, int64_t nrhs, hipStream_t s);
+// middle weights, 16-column activation chunks, r = 16 (FP32)
+hipError_t launch_grad_middle(const bf_plan *p, const void *dz, const void *y, void *grad,
+                              int64_t nrhs, hipStream_t s);
 hipError_t launch_grad_leaf_mfma(const bf_plan *p, const void *user, int64_t ld, const void *act,
                                  void *grad, int64_t nrhs, hipStream_t s);
 

@@ -1,0 +1,158 @@
+// One butterfly level as an FP32 matrix-core product (per-level path, any radix R
+// and rank r with R r = 32, 64 or 128 and r even).
+//
+// Butterfly b of a level combines R input slots into R output slots through one
+// (R r) x (R r) complex block M (Sec. 3.2.1 and 3.2.2: the blocks of G^l, and of
+// the conjugate transposes of H^l):
+//   direct  M[co r + a][ci r + k] = Fb[R hi + co][lo][a][ci r + k]
+//   tconj   M[co r + a][ci r + k] = conj(Fb[R hi + ci][lo][k][co r + a])
+// with b = hi blo + lo.  The product is the real contraction
+//   Re y = [Re M, -Im M] [Re x; Im x],  Im y = [Re M, -Im M] [Im x; -Re x]
+// on v_mfma_f32_32x32x2_f32.  One workgroup per butterfly, R r / 32 wavefronts;
+// wavefront w computes output rows 32 w .. 32 w + 31 and keeps its rows of the
+// real block ([Re M, -Im M], 2 R r values per row) in registers; the workgroup
+// walks the 32-column activation chunks, staging each chunk's R r x 32 complex
+// inputs in LDS as [K index][column] (real parts, then imaginary parts).
+#include <hip/hip_runtime.h>
+
+#include "bf_internal.h"
+
+namespace bfly {
+namespace {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// A operand of step s (K indices 2 s, 2 s + 1) for lane (i, kk): real block row
+// 32 w + i, K index 2 s + kk; stored as [b][w][s / 4][lane][s % 4].
+__global__ void k_pack_level_mfma(const float2 *__restrict__ Fb, float *__restrict__ out, int64_t nb,
+                                  int64_t blo, int R, int r, int tconj) {
+  const int BR = R * r;
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= nb * (int64_t)BR * 2 * BR) return;
+  const int sl = (int)(t & 3);
+  const int lane = (int)((t >> 2) & 63);
+  const int64_t q = t >> 8;             // (b, w, s / 4)
+  const int s4 = (int)(q % (BR / 4));   // s / 4
+  const int64_t bw = q / (BR / 4);      // b * (BR / 32) + w
+  const int w = (int)(bw % (BR / 32));
+  const int64_t b = bw / (BR / 32);
+  const int s = 4 * s4 + sl;
+  const int o = 32 * w + (lane & 31);
+  const int k2 = 2 * s + (lane >> 5);   // 0 .. 2 BR - 1
+  const int part = k2 >= BR ? 1 : 0, kin = k2 - part * BR;
+  const int64_t hi = b / blo, lo = b - hi * blo;
+  const int co = o / r, a = o - co * r, ci = kin / r, k = kin - ci * r;
+  float2 m;
+  if (tconj) {
+    m = Fb[(((R * hi + ci) * blo + lo) * r + k) * BR + co * r + a];
+    m.y = -m.y;
+  } else {
+    m = Fb[(((R * hi + co) * blo + lo) * r + a) * BR + ci * r + k];
+  }
+  out[t] = part == 0 ? m.x : -m.y;
+}
+
+template <int BR>
+__global__ __launch_bounds__(BR * 2) void k_level_mfma(const f32x4 *__restrict__ Ap,
+                                                        const f32x4 *__restrict__ x,
+                                                        f32x4 *__restrict__ y, int64_t blo,
+                                                        int64_t nslots, int64_t nchunks, int R,
+                                                        int r, int strided_in) {
+  constexpr int W = BR / 32;
+  __shared__ float xs[2 * BR][32];
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t b = blockIdx.x;
+  const int64_t hi = b / blo, lo = b - hi * blo;
+  auto slot = [&](int c, bool strided) {
+    return strided ? hi * R * blo + c * blo + lo : hi * R * blo + R * lo + c;
+  };
+  // this wavefront's rows of the real block: a[s] = A[32 w + i][2 s + kk]
+  float a[BR];
+  {
+    const f32x4 *src = Ap + (b * W + w) * (BR / 4) * 64 + lane;
+#pragma unroll
+    for (int s4 = 0; s4 < BR / 4; ++s4) {
+      const f32x4 v = src[s4 * 64];
+      a[4 * s4] = v.x;
+      a[4 * s4 + 1] = v.y;
+      a[4 * s4 + 2] = v.z;
+      a[4 * s4 + 3] = v.w;
+    }
+  }
+  const int half = r / 2;  // row pairs per slot
+  const int j = lane & 31, kk = lane >> 5;
+  for (int64_t ch = 0; ch < nchunks; ++ch) {
+    __syncthreads();  // the previous chunk's inputs are no longer read
+    // stage: R slots x r/2 pairs x 32 columns, 16 bytes each (rows 2p, 2p + 1)
+    for (int pc = threadIdx.x; pc < BR * 16; pc += BR * 2) {
+      const int n = pc & 31, cp = pc >> 5;  // cp = c * half + p
+      const int c = cp / half, p = cp - c * half;
+      const f32x4 v = x[((ch * nslots + slot(c, strided_in != 0)) * half + p) * 32 + n];
+      const int row = c * r + 2 * p;
+      xs[row][n] = v.x;
+      xs[BR + row][n] = v.y;
+      xs[row + 1][n] = v.z;
+      xs[BR + row + 1][n] = v.w;
+    }
+    __syncthreads();
+    floatx16 dre = {}, dim = {};
+#pragma unroll
+    for (int s = 0; s < BR; ++s) {
+      const int k = 2 * s + kk;
+      const float bre = xs[k][j];
+      const float bim = (2 * s < BR) ? xs[k + BR][j] : -xs[k - BR][j];
+      dre = __builtin_amdgcn_mfma_f32_32x32x2f32(a[s], bre, dre, 0, 0, 0);
+      dim = __builtin_amdgcn_mfma_f32_32x32x2f32(a[s], bim, dim, 0, 0, 0);
+    }
+    // lane (j, eta) holds rows 32 w + 8 q + 4 eta + v of column j
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int v = 0; v < 4; v += 2) {
+        const int o = 32 * w + 8 * q + 4 * kk + v;
+        const int co = o / r, row = o - co * r;
+        const f32x4 val = {dre[4 * q + v], dim[4 * q + v], dre[4 * q + v + 1], dim[4 * q + v + 1]};
+        y[((ch * nslots + slot(co, strided_in == 0)) * half + row / 2) * 32 + j] = val;
+      }
+  }
+}
+
+}  // namespace
+
+bool level_mfma_supported(int R, int r) {
+  const int BR = R * r;
+  return (BR == 32 || BR == 64 || BR == 128) && r % 2 == 0;
+}
+
+hipError_t launch_pack_level_mfma(const LevelOp &op, int R, int r, void *out, hipStream_t s) {
+  const int BR = R * r;
+  const int64_t total = op.nb * (int64_t)BR * 2 * BR;
+  const int bs = 256;
+  hipLaunchKernelGGL(k_pack_level_mfma, dim3((unsigned)((total + bs - 1) / bs)), dim3(bs), 0, s,
+                     (const float2 *)op.mat, (float *)out, op.nb, op.blo, R, r, op.tconj ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_level_mfma(const bf_plan *p, const LevelOp &op, const void *in, void *out,
+                             int64_t nrhs, hipStream_t s) {
+  const int BR = p->R * p->r;
+  const int64_t nchunks = (nrhs + 31) / 32;
+  const int strided = op.mode == kStridedIn ? 1 : 0;
+  const f32x4 *A = static_cast<const f32x4 *>(op.packed);
+  const f32x4 *x = static_cast<const f32x4 *>(in);
+  f32x4 *y = static_cast<f32x4 *>(out);
+  if (BR == 32)
+    hipLaunchKernelGGL(k_level_mfma<32>, dim3((unsigned)op.nb), dim3(64), 0, s, A, x, y, op.blo, p->P,
+                       nchunks, p->R, p->r, strided);
+  else if (BR == 64)
+    hipLaunchKernelGGL(k_level_mfma<64>, dim3((unsigned)op.nb), dim3(128), 0, s, A, x, y, op.blo, p->P,
+                       nchunks, p->R, p->r, strided);
+  else
+    hipLaunchKernelGGL(k_level_mfma<128>, dim3((unsigned)op.nb), dim3(256), 0, s, A, x, y, op.blo, p->P,
+                       nchunks, p->R, p->r, strided);
+  return hipGetLastError();
+}
+
+}  // namespace bfly

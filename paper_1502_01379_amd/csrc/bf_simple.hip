@@ -96,6 +96,59 @@ __global__ void k_leaf_out(const typename Cx<T>::type *__restrict__ W,
   u[(i * n0 + p) * ld + n] = acc;
 }
 
+// The same two leaf products with one thread per (leaf, column): the thread
+// keeps the leaf's N0 input rows (leaf-in) or RR rank rows (leaf-out) of its
+// column in registers and produces every output row, so each input is read once.
+template <class T, int N0>
+__global__ void k_leaf_in_col(const typename Cx<T>::type *__restrict__ W,
+                              const typename Cx<T>::type *__restrict__ x, int64_t ld,
+                              typename Cx<T>::type *__restrict__ y, int64_t P, int r, int64_t nrhs,
+                              int64_t npad, int cs) {
+  using C = typename Cx<T>::type;
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= P * npad) return;
+  const int64_t n = t % npad, j = t / npad;
+  C v[N0];
+#pragma unroll
+  for (int p = 0; p < N0; ++p) v[p] = n < nrhs ? x[(j * N0 + p) * ld + n] : C{0, 0};
+  const C *w = W + j * N0 * r;
+  for (int a = 0; a < r; ++a) {
+    C acc{0, 0};
+#pragma unroll
+    for (int p = 0; p < N0; ++p) {
+      const C c = cmulc(v[p], w[p * r + a]);
+      acc.x += c.x;
+      acc.y += c.y;
+    }
+    y[act_off(j, a, n, P, r, cs)] = acc;
+  }
+}
+
+template <class T, int RR>
+__global__ void k_leaf_out_col(const typename Cx<T>::type *__restrict__ W,
+                               const typename Cx<T>::type *__restrict__ z,
+                               typename Cx<T>::type *__restrict__ u, int64_t ld, int64_t P, int n0,
+                               int64_t nrhs, int cs) {
+  using C = typename Cx<T>::type;
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= P * nrhs) return;
+  const int64_t n = t % nrhs, i = t / nrhs;
+  C v[RR];
+#pragma unroll
+  for (int a = 0; a < RR; ++a) v[a] = z[act_off(i, a, n, P, RR, cs)];
+  for (int p = 0; p < n0; ++p) {
+    const C *w = W + (i * n0 + p) * RR;
+    C acc{0, 0};
+#pragma unroll
+    for (int a = 0; a < RR; ++a) {
+      const C c = cmul(w[a], v[a]);
+      acc.x += c.x;
+      acc.y += c.y;
+    }
+    u[(i * n0 + p) * ld + n] = acc;
+  }
+}
+
 // One butterfly level: thread per (butterfly, output row, column).  Fb is the
 // canonical level array [R^(l+1)][blo][r][R r].  With o = c_out r + a_out and
 // k = c_in r + b_in the block entry is
@@ -240,6 +293,16 @@ hipError_t level_op_t(const bf_plan *p, const LevelOp &op, const void *in, int64
   const int bs = 256;
   switch (op.kind) {
     case LevelOp::kLeafIn:
+      if (p->n0 == 16 || p->n0 == 4) {
+        const dim3 grid(blocks_for(p->P * npad, bs));
+        if (p->n0 == 16)
+          hipLaunchKernelGGL((k_leaf_in_col<T, 16>), grid, dim3(bs), 0, s, (const C *)op.mat,
+                             (const C *)in, ld_in, (C *)out, p->P, p->r, nrhs, npad, cs);
+        else
+          hipLaunchKernelGGL((k_leaf_in_col<T, 4>), grid, dim3(bs), 0, s, (const C *)op.mat,
+                             (const C *)in, ld_in, (C *)out, p->P, p->r, nrhs, npad, cs);
+        break;
+      }
       hipLaunchKernelGGL(k_leaf_in<T>, dim3(blocks_for(p->P * p->r * npad, bs)), dim3(bs), 0, s,
                          (const C *)op.mat, (const C *)in, ld_in, (C *)out, p->P, p->n0, p->r,
                          nrhs, npad, cs);
@@ -256,6 +319,19 @@ hipError_t level_op_t(const bf_plan *p, const LevelOp &op, const void *in, int64
                          op.tconj ? 1 : 0, npad, cs);
       break;
     case LevelOp::kLeafOut:
+      if (p->r == 32 || p->r == 16 || p->r == 8) {
+        const dim3 grid(blocks_for(p->P * nrhs, bs));
+        if (p->r == 32)
+          hipLaunchKernelGGL((k_leaf_out_col<T, 32>), grid, dim3(bs), 0, s, (const C *)op.mat,
+                             (const C *)in, (C *)out, ld_out, p->P, p->n0, nrhs, cs);
+        else if (p->r == 16)
+          hipLaunchKernelGGL((k_leaf_out_col<T, 16>), grid, dim3(bs), 0, s, (const C *)op.mat,
+                             (const C *)in, (C *)out, ld_out, p->P, p->n0, nrhs, cs);
+        else
+          hipLaunchKernelGGL((k_leaf_out_col<T, 8>), grid, dim3(bs), 0, s, (const C *)op.mat,
+                             (const C *)in, (C *)out, ld_out, p->P, p->n0, nrhs, cs);
+        break;
+      }
       hipLaunchKernelGGL(k_leaf_out<T>, dim3(blocks_for(p->P * p->n0 * nrhs, bs)), dim3(bs), 0,
                          s, (const C *)op.mat, (const C *)in, (C *)out, ld_out, p->P, p->n0,
                          p->r, nrhs, cs);
@@ -268,6 +344,8 @@ hipError_t level_op_t(const bf_plan *p, const LevelOp &op, const void *in, int64
 
 hipError_t launch_level_op(const bf_plan *p, const LevelOp &op, const void *in, int64_t ld_in,
                            void *out, int64_t ld_out, int64_t nrhs, hipStream_t s) {
+  if (op.kind == LevelOp::kButterfly && op.packed && p->cs == 5)
+    return launch_level_mfma(p, op, in, out, nrhs, s);
   if (p->prec == BF_PREC_F64) return level_op_t<double>(p, op, in, ld_in, out, ld_out, nrhs, s);
   return level_op_t<float>(p, op, in, ld_in, out, ld_out, nrhs, s);
 }

@@ -160,3 +160,42 @@ def test_full_size_fio_65536_f32(dev):
     cols = [0, 17, 63]
     ref = oracle.bf_apply(f, g[:, cols])
     assert oracle.rel_err(u[:, cols], ref) < TOL["f32"]
+
+
+def test_full_size_grt_radix4_65536_f32(dev):
+    # the 2D generalized Radon transform shape: 256 x 256 points (N = 65536), quadtrees
+    # with 4 x 4 leaves (radix 4, L = 6), r = 32, 128 right-hand sides; synthetic factors
+    # of those shapes; apply and adjoint on sampled columns against the oracle
+    f = synthetic_factors(4, 16, 6, 32, seed=13)
+    N = 65536
+    g = complex_gaussian((N, 128), 14)
+    h = _handle(f, "f32")
+    gd = _to(g, dev, "f32")
+    u = h.apply(gd).cpu().numpy()
+    v = h.apply_adjoint(gd).cpu().numpy()
+    cols = [0, 77, 127]
+    assert oracle.rel_err(u[:, cols], oracle.bf_apply(f, g[:, cols])) < TOL["f32"]
+    assert oracle.rel_err(v[:, cols], oracle.bf_apply_adjoint(f, g[:, cols])) < TOL["f32"]
+
+
+@pytest.mark.parametrize("radix,leaf,L,r", [(4, 16, 2, 8), (4, 4, 4, 16), (2, 8, 6, 32),
+                                             (4, 16, 4, 32), (2, 16, 4, 64)])
+@pytest.mark.parametrize("nrhs", [1, 31, 70])
+def test_level_mfma_shapes(dev, radix, leaf, L, r, nrhs):
+    # per-level butterflies on the matrix cores (R r = 32, 64, 128 blocks; both slot
+    # patterns; ragged 32-column chunks), apply, adjoint and backward, FP32
+    f = synthetic_factors(radix, leaf, L, r, seed=7 * radix + L + r)
+    N = leaf * radix ** L
+    g = complex_gaussian((N, nrhs), r + nrhs)
+    gu = complex_gaussian((N, nrhs), r + nrhs + 1)
+    h = _handle(f, "f32")
+    assert h.path == 0
+    u = h.apply(_to(g, dev, "f32")).cpu().numpy()
+    assert oracle.rel_err(u, oracle.bf_apply(f, g)) < TOL["f32"]
+    v = h.apply_adjoint(_to(g, dev, "f32")).cpu().numpy()
+    assert oracle.rel_err(v, oracle.bf_apply_adjoint(f, g)) < TOL["f32"]
+    grad_g, grads = h.backward(_to(g, dev, "f32"), _to(gu, dev, "f32"))
+    ref = oracle.bf_grad(f, g, gu)
+    assert oracle.rel_err(grad_g.cpu().numpy(), ref["g"]) < TOL["f32"]
+    for a, b in zip(_flat_grads(grads, h), _flat_grads(ref, h)):
+        assert oracle.rel_err(a.cpu().numpy(), b) < 10 * TOL["f32"]
