@@ -24,6 +24,6 @@ Contents, each written from the paper's text:
 """
 from . import kernels, lowrank, construct, apply, sparse, metrics  # noqa: F401
 from .kernels import Kernel1D, Kernel2D, fourier, fio, grt2d  # noqa: F401
-from .construct import construct_factors  # noqa: F401
+from .construct import construct_factors, construct_factors_matvec  # noqa: F401
 from .apply import bf_apply, bf_apply_adjoint, bf_grad  # noqa: F401
 from .metrics import rel_err  # noqa: F401

@@ -62,6 +62,11 @@ def _pivoted_qr(A):
     return Q, Rm, piv
 
 
+def pivoted_qr_q(A):
+    """Q factor of LAPACK's pivoted QR (geqp3) of A (Alg. 2.1, step 2)."""
+    return _pivoted_qr(A)[0]
+
+
 def _qr_pivots(A):
     """Column order chosen by LAPACK's pivoted QR (geqp3) of A."""
     _, piv = sla.qr(A, mode="r", pivoting=True)

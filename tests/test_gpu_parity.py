@@ -199,3 +199,22 @@ def test_level_mfma_shapes(dev, radix, leaf, L, r, nrhs):
     assert oracle.rel_err(grad_g.cpu().numpy(), ref["g"]) < TOL["f32"]
     for a, b in zip(_flat_grads(grads, h), _flat_grads(ref, h)):
         assert oracle.rel_err(a.cpu().numpy(), b) < 10 * TOL["f32"]
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16x3"])
+def test_hankel_sum_workload(dev, prec):
+    # Example 2 of Sec. 4 (sums of Hankel functions H^(1)_nu(x)) through the same fused
+    # apply: parity with the oracle on identical factors, and the approximation error
+    # against the dense sum matches the oracle's
+    kern = kernels.HankelSum(1024)
+    f = oracle.construct_factors(kern, leaf=16, r=16, method="sampling", seed=2)
+    g = complex_gaussian((kern.N, 16), 3)
+    h = _handle(f, prec)
+    assert h.path == 1
+    u = h.apply(_to(g, dev, prec)).cpu().numpy()
+    ref = oracle.bf_apply(f, g)
+    assert oracle.rel_err(u, ref) < TOL[prec]
+    rows = np.arange(0, kern.N, 4)
+    dense = kernels.dense_apply_rows(kern, rows, g)
+    e_gpu, e_ora = oracle.rel_err(u[rows], dense), oracle.rel_err(ref[rows], dense)
+    assert abs(e_gpu - e_ora) <= 2 * TOL[prec] + 1e-3 * e_ora

@@ -139,3 +139,65 @@ def test_middle_form_drops_null_directions():
     U, S, V = lowrank.form_usv(U0, s, V0h)
     assert np.all(np.isfinite(S)) and S[0] == 0.5 and S[1] == 0 and S[2] == 0
     assert np.abs(U @ np.diag(S) @ V.conj().T - U0[:, :1] @ V0h[:1] * 2).max() < 1e-15
+
+
+# ---- construction from products with K and K^* (Alg. 2.1, first case of Sec. 3.1)
+
+def _fourier_fft_box(N):
+    # K_{jk} = (-1)^j e^{2 pi i j k / N}: K g = (-1)^j N ifft(g), K^* w = fft((-1)^j w)
+    sign = (-1.0) ** np.arange(N)
+    return (lambda X: sign[:, None] * N * np.fft.ifft(X, axis=0),
+            lambda X: np.fft.fft(sign[:, None] * X, axis=0))
+
+
+def test_matvec_construction_full_rank_is_exact():
+    # r >= every block dimension: the sketches span every block, so K_BF = K
+    kern = kernels.fio(64)
+    K = kernels.dense_matrix(kern)
+    f = oracle.construct_factors_matvec(64, 2, 4, 16, lambda X: K @ X, lambda X: K.conj().T @ X,
+                                        seed=3)
+    assert _err_vs_dense(kern, f) < 1e-12
+
+
+def test_matvec_construction_recovers_an_exact_butterfly():
+    # K is itself a butterfly of rank 3: every middle block and every recursion block
+    # has rank <= 3, so rank 5 reproduces K up to rounding
+    from bf_inputs import synthetic_factors
+    fs = synthetic_factors(2, 4, 6, 3, seed=5)
+    N = 256
+    K = oracle.bf_apply(fs, np.eye(N, dtype=complex))
+    f = oracle.construct_factors_matvec(N, 2, 4, 5, lambda X: K @ X, lambda X: K.conj().T @ X,
+                                        seed=6)
+    assert oracle.rel_err(oracle.bf_apply(f, np.eye(N)), K) < 1e-11
+
+
+def test_matvec_construction_with_fft_black_box():
+    # the Fourier kernel through the FFT only (K is never formed): the same factors as
+    # with the dense black box up to rounding, and the accuracy of the entry-sampling
+    # route at the same rank
+    N, r = 1024, 24
+    kern = kernels.fourier(N)
+    K = kernels.dense_matrix(kern)
+    mv, rmv = _fourier_fft_box(N)
+    g = complex_gaussian((N, 3), 8)
+    assert oracle.rel_err(mv(g), K @ g) < 1e-13 and oracle.rel_err(rmv(g), K.conj().T @ g) < 1e-13
+    f_fft = oracle.construct_factors_matvec(N, 2, 16, r, mv, rmv, seed=9)
+    f_dense = oracle.construct_factors_matvec(N, 2, 16, r, lambda X: K @ X,
+                                              lambda X: K.conj().T @ X, seed=9)
+    u_fft, u_dense = oracle.bf_apply(f_fft, g), oracle.bf_apply(f_dense, g)
+    assert oracle.rel_err(u_fft, u_dense) < 1e-9
+    e_mv = oracle.rel_err(u_fft, K @ g)
+    e_s = _err_vs_dense(kern, construct_factors(kern, leaf=16, r=r, method="sampling", seed=0), 3, 8)
+    assert e_mv < 1e-3 and e_mv < 10 * e_s
+
+
+def test_middle_from_sketches_is_exact_for_low_rank_blocks():
+    rng = np.random.default_rng(4)
+    A = (rng.standard_normal((40, 6)) + 1j * rng.standard_normal((40, 6)))
+    B = (rng.standard_normal((30, 6)) + 1j * rng.standard_normal((30, 6)))
+    Z = A @ B.conj().T                                   # rank 6
+    C = rng.standard_normal((30, 13)) + 1j * rng.standard_normal((30, 13))
+    Rr = rng.standard_normal((40, 13)) + 1j * rng.standard_normal((40, 13))
+    U0, s, V0h = oracle.construct.middle_from_sketches(Z @ C, Z.conj().T @ Rr, C, 8)
+    assert np.linalg.norm(U0 * s @ V0h - Z) < 1e-12 * np.linalg.norm(Z)
+    assert np.all(np.diff(s) <= 1e-12)                   # decreasing
