@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 1 GiB device copy (reference for HBM byte counters)")
+    ap.add_argument("--construct", action="store_true",
+                    help="time the construction from products of K F K instead of the apply")
     ap.add_argument("--backward", action="store_true",
                     help="time bf_backward (gradients for every factor block and g) instead")
     return ap.parse_args()
@@ -114,6 +116,52 @@ def bench_backward(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_construct(args):
+    """Construction from products with K and K^* (the first case of Sec. 3.1) of the
+    composition K~ = K F K (Sec. 4 Example 3) at N = 2^log2n: K is a butterfly
+    factorization applied by this library (seeded synthetic FIO-shaped factors,
+    FP32), F an FFT.  Reports the time of the black-box products (GPU) and of the
+    host FP64 linear algebra."""
+    import torch
+    from bf_inputs import synthetic_factors
+    from paper_1502_01379_amd import BFHandle
+    from paper_1502_01379_amd.construct import construct_from_products
+    L = args.log2n - 4
+    N = 16 * 2 ** L
+    r = 16
+    hK = BFHandle(synthetic_factors(2, 16, L, r, seed=40), "f32")
+    sign = torch.tensor((-1.0) ** np.arange(N), dtype=torch.float32, device="cuda")[:, None]
+    t_box = [0.0]
+
+    def timed(fn):
+        def run(X):
+            torch.cuda.synchronize()
+            t = time.time()
+            Y = fn(X.to(torch.complex64).contiguous())
+            torch.cuda.synchronize()
+            t_box[0] += time.time() - t
+            return Y
+        return run
+
+    # K~ X = K F K X with (F v)_k = sum_j e^{-2 pi i x_j xi_k} v_j = fft((-1)^j v)
+    mv = timed(lambda X: hK.apply(torch.fft.fft(hK.apply(X) * sign, dim=0).contiguous()))
+    rmv = timed(lambda X: hK.apply_adjoint(
+        (torch.fft.ifft(hK.apply_adjoint(X), dim=0) * (N * sign)).contiguous()))
+    t0 = time.time()
+    f = construct_from_products(N, 2, 16, r, mv, rmv, seed=1)
+    total = time.time() - t0
+    h2 = BFHandle(f, "bf16x3")
+    m = 2 ** (L // 2)
+    out = {"metric": "construction seconds from products with K and K^* (K F K)",
+           "value": total, "unit": "s", "higher_is_better": False, "data": "synthetic",
+           "config": {"workload": f"K F K with K a 1D FIO-shaped factorization, N=2^{args.log2n}, "
+                                  f"leaf 16, r={r}, oversampling 5", "N": N, "r": r,
+                      "product_columns": 2 * m * (r + 5)},
+           "black_box_seconds": t_box[0], "host_fp64_seconds": total - t_box[0],
+           "handle_path": h2.path}
+    print(json.dumps(out), flush=True)
+
+
 def pass_work(name, L, r, leaf, nrhs, K, has_leaf, has_middle):
     """Algorithmic flops and compulsory HBM bytes of one fused-pass launch.
 
@@ -161,6 +209,9 @@ def main():
         sys.exit(2)
     if args.backward:
         bench_backward(args)
+        return
+    if args.construct:
+        bench_construct(args)
         return
     import torch
 

@@ -1,0 +1,173 @@
+"""Butterfly factorization of an operator known only through products with K and K^*.
+
+This is the first case of Sec. 3.1: the middle level is factorized by the
+randomized SVD of Sec. 2.1 (Algorithm 2.1) from two products with block-diagonal
+Gaussian matrices, and the factors of the middle level are then factorized
+recursively as in Sec. 3.2.  The products are a caller-supplied black box on the
+GPU (for instance this library's ``bf_apply`` composed with an FFT, Sec. 4
+Example 3); the linear algebra runs on the host in FP64, as the construction's
+stability needs.
+
+    f = construct_from_products(N, radix, leaf, r, apply, apply_adjoint)
+    h = BFHandle(f, "bf16x3")
+
+``apply(X)`` and ``apply_adjoint(X)`` take and return device tensors of shape
+[N][k] (complex64 or complex128); the result is the canonical host factor set
+that ``bf_create_from_factors`` takes.
+"""
+from __future__ import annotations
+
+import os
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import scipy.linalg as sla
+
+
+def _depth(N, leaf, radix):
+    P, rem = divmod(int(N), int(leaf))
+    L = int(round(np.log(P) / np.log(radix))) if P > 1 else 0
+    if rem or radix ** L != P:
+        raise ValueError("N / leaf must be a power of the radix")
+    if L % 2:
+        raise ValueError("the tree depth must be even")
+    return L
+
+
+def _threads():
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+def _one_blas_thread():
+    """BLAS/LAPACK single-threaded while the work is spread over Python threads."""
+    try:
+        from threadpoolctl import threadpool_limits
+        return threadpool_limits(1)
+    except Exception:  # threadpoolctl missing: leave the BLAS pool as it is
+        import contextlib
+        return contextlib.nullcontext()
+
+
+def _batched_svd(Z):
+    """np.linalg.svd over the leading axes, split over threads (LAPACK runs without
+    the interpreter lock)."""
+    flat = Z.reshape((-1,) + Z.shape[-2:])
+    n = flat.shape[0]
+    nt = min(_threads(), n)
+    if nt <= 1 or n < 8:
+        return np.linalg.svd(Z, full_matrices=False)
+    cuts = np.linspace(0, n, nt + 1).astype(int)
+    with _one_blas_thread(), ThreadPoolExecutor(nt) as ex:
+        parts = list(ex.map(lambda q: np.linalg.svd(flat[cuts[q]:cuts[q + 1]], full_matrices=False),
+                            range(nt)))
+    U = np.concatenate([a[0] for a in parts]).reshape(Z.shape[:-1] + (parts[0][0].shape[-1],))
+    s = np.concatenate([a[1] for a in parts]).reshape(Z.shape[:-2] + (parts[0][1].shape[-1],))
+    Vh = np.concatenate([a[2] for a in parts]).reshape(Z.shape[:-2] + parts[0][2].shape[-2:])
+    return U, s, Vh
+
+
+def _svd_rank(Z, r):
+    """Batched rank-r truncated SVD over the leading axes, zero-padded to r."""
+    U, s, Vh = _batched_svd(Z)
+    k = min(r, s.shape[-1])
+    U0 = np.zeros(Z.shape[:-1] + (r,), dtype=np.complex128)
+    s0 = np.zeros(Z.shape[:-2] + (r,))
+    V0h = np.zeros(Z.shape[:-2] + (r, Z.shape[-1]), dtype=np.complex128)
+    U0[..., :k] = U[..., :k]
+    s0[..., :k] = s[..., :k]
+    V0h[..., :k, :] = Vh[..., :k, :]
+    return U0, s0, V0h
+
+
+def _middle_block(Y, W, C, r):
+    """Rank-r SVD of Z = K^h_ij from Y = Z C and W = Z^* R (Alg. 2.1).
+
+    Q_col and Q_row are the first r columns of the pivoted-QR Q factors of Y and
+    W.  The middle matrix Q_col^* Z Q_row is taken from the sketches alone:
+    Z ~ Z Q_row Q_row^* gives Q_col^* Y = M (Q_row^* C), solved in the least
+    squares sense.
+    """
+    Qc = sla.qr(Y, mode="economic", pivoting=True)[0][:, :r]
+    Qr = sla.qr(W, mode="economic", pivoting=True)[0][:, :r]
+    M = np.linalg.lstsq((Qr.conj().T @ C).T, (Qc.conj().T @ Y).T, rcond=1e-14)[0].T
+    Um, sm, Vmh = _svd_rank(M, r)
+    return Qc @ Um, sm, Vmh @ Qr.conj().T
+
+
+def _recursive(Wb, R, r, levels):
+    """Sec. 3.2.1 for every middle-level node at once.
+
+    Wb[node][j][rows][r] holds the column blocks U^h_{node, j} (or V^h).  At each
+    level the rows of child c of every node, over R consecutive column blocks,
+    are approximated in the third form U0 S0 . V0^* (batched SVD).  Returns the
+    per-level block arrays [node, child-path, j'][r][R r] flattened to the
+    canonical order and the leaf blocks.
+    """
+    cur = Wb                                   # [nodes][nb][rows][r]
+    blocks = []
+    for _ in range(levels):
+        nodes, nb, rows, _ = cur.shape
+        crow = rows // R
+        # Z[a, c, jp] = [cur[a, R jp + cc, c rows] for cc] -> [nodes][R][nb/R][crow][R r]
+        Z = cur.reshape(nodes, nb // R, R, R, crow, r)          # [a][jp][cc][c][crow][r]
+        Z = Z.transpose(0, 3, 1, 4, 2, 5).reshape(nodes, R, nb // R, crow, R * r)
+        U0, s, V0h = _svd_rank(Z, r)
+        blocks.append(V0h.reshape(nodes * R, nb // R, r, R * r))
+        cur = (U0 * s[..., None, :]).reshape(nodes * R, nb // R, crow, r)
+    return blocks, cur[:, 0]
+
+
+def construct_from_products(N, radix, leaf, r, apply, apply_adjoint, p=5, seed=0, drop_rel=1e-14,
+                            device="cuda"):
+    """Canonical factors of K (see the module docstring); the test matrices are
+    passed to the black box as tensors on `device`."""
+    import torch
+
+    R = int(radix)
+    L = _depth(N, leaf, R)
+    h = L // 2
+    m = R ** h
+    b = N // m
+    k = r + p
+    rng = np.random.default_rng(seed)
+    Cb = (rng.standard_normal((m, b, k)) + 1j * rng.standard_normal((m, b, k))) / np.sqrt(2)
+    Rb = (rng.standard_normal((m, b, k)) + 1j * rng.standard_normal((m, b, k))) / np.sqrt(2)
+
+    probe = apply(torch.zeros((N, 1), dtype=torch.complex128, device=device))
+    dt = probe.dtype
+
+    def block_diag(blocks):
+        # N x m k with block j (rows j b .., columns j k ..) = blocks[j], built on the device
+        X = torch.zeros((m, b, m, k), dtype=dt, device=device)
+        idx = torch.arange(m, device=device)
+        X[idx, :, idx, :] = torch.from_numpy(blocks).to(device, dt)
+        return X.reshape(N, m * k)
+
+    KC = apply(block_diag(Cb)).cpu().numpy().astype(np.complex128)
+    KR = apply_adjoint(block_diag(Rb)).cpu().numpy().astype(np.complex128)
+
+    # middle level: K^h_ij ~ U^h_ij S^h_ij (V^h_ji)^*, first form of Sec. 2
+    Uh = np.zeros((m, m, b, r), dtype=np.complex128)   # [i][j]
+    Vh = np.zeros((m, m, b, r), dtype=np.complex128)   # [j][i]
+    S = np.zeros((m, m, r))
+
+    def row(i):
+        for j in range(m):
+            U0, s, V0h = _middle_block(KC[i * b:(i + 1) * b, j * k:(j + 1) * k],
+                                       KR[j * b:(j + 1) * b, i * k:(i + 1) * k], Cb[j], r)
+            keep = (s > 0) & (s > drop_rel * s[0])
+            sk = np.where(keep, s, 0.0)
+            Uh[i, j] = U0 * sk
+            Vh[j, i] = (V0h * sk[:, None]).conj().T
+            S[i, j] = np.where(keep, 1.0 / np.where(keep, s, 1.0), 0.0)
+
+    with _one_blas_thread(), ThreadPoolExecutor(min(_threads(), m)) as ex:
+        list(ex.map(row, range(m)))
+
+    lv = L - h
+    Gb, UL = _recursive(Uh, R, r, lv)
+    Hb, VL = _recursive(Vh, R, r, lv)
+    # the node of depth t below middle node i with child path c is R^(t+1) i + path:
+    # _recursive already orders its outputs that way
+    return {"radix": R, "leaf": int(leaf), "L": L, "r": int(r),
+            "VL": VL, "UL": UL, "S": S, "H": Hb, "G": Gb}
