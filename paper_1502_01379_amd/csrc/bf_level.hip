@@ -11,8 +11,9 @@
 // on v_mfma_f32_32x32x2_f32.  One workgroup per butterfly, R r / 32 wavefronts;
 // wavefront w computes output rows 32 w .. 32 w + 31 and keeps its rows of the
 // real block ([Re M, -Im M], 2 R r values per row) in registers; the workgroup
-// walks the 32-column activation chunks, staging each chunk's R r x 32 complex
-// inputs in LDS as [K index][column] (real parts, then imaginary parts).
+// walks the 32-column activation chunks, copying each chunk's R r x 32 complex
+// inputs into LDS in their activation layout with global -> LDS loads, one chunk
+// ahead of the one being contracted.
 #include <hip/hip_runtime.h>
 
 #include "bf_internal.h"
@@ -60,14 +61,29 @@ __global__ __launch_bounds__(BR * 2) void k_level_mfma(const f32x4 *__restrict__
                                                         int64_t nslots, int64_t nchunks, int R,
                                                         int r, int strided_in) {
   constexpr int W = BR / 32;
-  __shared__ float xs[2 * BR][32];
+  constexpr int kChunkBytes = BR * 32 * 8;  // R slots x r rows x 32 columns, complex64
+  // two chunk buffers in the activation layout: [slot c][row pair p][column n] x 16 B
+  // (rows 2p and 2p + 1 of column n, real and imaginary parts)
+  __shared__ __attribute__((aligned(16))) char xs[2][kChunkBytes];
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t b = blockIdx.x;
   const int64_t hi = b / blo, lo = b - hi * blo;
+  const int half = r / 2;  // row pairs per slot
   auto slot = [&](int c, bool strided) {
     return strided ? hi * R * blo + c * blo + lo : hi * R * blo + R * lo + c;
   };
+  // one chunk: R slots of half * 32 pieces, contiguous in global memory per slot
+  auto issue = [&](int64_t ch) {
+    char *dst = xs[ch & 1];
+    for (int pc = threadIdx.x; pc < BR * 16; pc += BR * 2) {
+      const int c = pc / (half * 32), rem = pc - c * half * 32;
+      const f32x4 *src = x + (ch * nslots + slot(c, strided_in != 0)) * half * 32 + rem;
+      __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)(dst + pc * 16),
+                                       16, 0, 0);
+    }
+  };
+  issue(0);
   // this wavefront's rows of the real block: a[s] = A[32 w + i][2 s + kk]
   float a[BR];
   {
@@ -81,28 +97,31 @@ __global__ __launch_bounds__(BR * 2) void k_level_mfma(const f32x4 *__restrict__
       a[4 * s4 + 3] = v.w;
     }
   }
-  const int half = r / 2;  // row pairs per slot
   const int j = lane & 31, kk = lane >> 5;
   for (int64_t ch = 0; ch < nchunks; ++ch) {
-    __syncthreads();  // the previous chunk's inputs are no longer read
-    // stage: R slots x r/2 pairs x 32 columns, 16 bytes each (rows 2p, 2p + 1)
-    for (int pc = threadIdx.x; pc < BR * 16; pc += BR * 2) {
-      const int n = pc & 31, cp = pc >> 5;  // cp = c * half + p
-      const int c = cp / half, p = cp - c * half;
-      const f32x4 v = x[((ch * nslots + slot(c, strided_in != 0)) * half + p) * 32 + n];
-      const int row = c * r + 2 * p;
-      xs[row][n] = v.x;
-      xs[BR + row][n] = v.y;
-      xs[row + 1][n] = v.z;
-      xs[BR + row + 1][n] = v.w;
-    }
-    __syncthreads();
+    // this chunk's copies (and the block rows) have landed; the previous chunk's eight
+    // output stores per lane, issued after them, may still be in flight
+    if (ch == 0)
+      __builtin_amdgcn_s_waitcnt(0);
+    else
+      __builtin_amdgcn_s_waitcnt(0xf78);  // vmcnt(8)
+    // everyone's copies have; the other buffer is free (a bare barrier: __syncthreads
+    // would also wait for the output stores still in flight)
+    __builtin_amdgcn_s_barrier();
+    if (ch + 1 < nchunks) issue(ch + 1);
+    const float *xc = reinterpret_cast<const float *>(xs[ch & 1]);
     floatx16 dre = {}, dim = {};
 #pragma unroll
     for (int s = 0; s < BR; ++s) {
-      const int k = 2 * s + kk;
-      const float bre = xs[k][j];
-      const float bim = (2 * s < BR) ? xs[k + BR][j] : -xs[k - BR][j];
+      // K index k = 2 s + kk of [Re x; Im x] (and of [Im x; -Re x]): input row
+      // 2 sp + kk with sp = s or s - BR / 2, i.e. row pair sp across the slots,
+      // which the buffer stores at (sp * 32 + j) * 16 bytes
+      const bool lo_half = 2 * s < BR;
+      const int sp = lo_half ? s : s - BR / 2;
+      const float *e = xc + (sp * 32 + j) * 4 + kk * 2;
+      const float xr = e[0], xi = e[1];
+      const float bre = lo_half ? xr : xi;
+      const float bim = lo_half ? xi : -xr;
       dre = __builtin_amdgcn_mfma_f32_32x32x2f32(a[s], bre, dre, 0, 0, 0);
       dim = __builtin_amdgcn_mfma_f32_32x32x2f32(a[s], bim, dim, 0, 0, 0);
     }

@@ -166,7 +166,7 @@ def _flat(d):
 
 
 @pytest.mark.parametrize("L", [2, 4, 6, 8, 10, 14])
-@pytest.mark.parametrize("prec", ["f32", "bf16x3"])
+@pytest.mark.parametrize("prec", ["f32", "bf16x3", "f16x3"])
 def test_fused_backward_tree_depths(dev, L, prec):
     # backward passes of one to four levels, one or two passes per side; every
     # gradient against the oracle, and recomputing the states inside the passes
