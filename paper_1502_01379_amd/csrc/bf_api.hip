@@ -500,18 +500,21 @@ bf_status backward_fused(bf_plan *p, const void *g, const void *grad_u, void *gr
   auto bptr = [&](int k) { return buf(ring0 + k % 6); };
   void *gout = grad_g ? grad_g : static_cast<void *>(ws + (size_t)nb * ab);
 
-  // forward pass j with copies of the states that have a buffer
-  auto run_forward = [&](int j, const char *tag) -> bf_status {
+  // forward pass j with copies of the states that have a buffer; a second run of a
+  // pass (recompute) only restores the states strictly inside it
+  auto run_forward = [&](int j, bool again) -> bf_status {
     const bfly::PassShape sh = bfly::fused_pass_shape(FP[j]);
+    if (again && sh.K == 1) return BF_OK;  // no state strictly inside a one-level pass
     void *lvl[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
-    for (int d = (sh.li || sh.mid) ? 0 : 1; d < sh.K; ++d) lvl[d] = aptr[td0[j] + d];
+    for (int d = (!again && (sh.li || sh.mid)) ? 0 : 1; d < sh.K; ++d) lvl[d] = aptr[td0[j] + d];
     const void *in = tin[j] < 0 ? g : aptr[tin[j]];
-    BWD_LAUNCH((*sh.name + tag).c_str(),
-               bfly::fused_run_pass(p, FP[j], in, aptr[td0[j] + sh.K], lvl, nrhs, ld, s));
+    void *out = again ? nullptr : aptr[td0[j] + sh.K];
+    BWD_LAUNCH((*sh.name + (again ? "_recompute" : "")).c_str(),
+               bfly::fused_run_pass(p, FP[j], in, out, lvl, nrhs, ld, s));
     return BF_OK;
   };
   for (int j = 0; j < np; ++j)
-    if ((st = run_forward(j, "")) != BF_OK) return st;
+    if ((st = run_forward(j, false)) != BF_OK) return st;
 
   // U^L: grad_UL = sum delta_u a_{2h+1}^*
   if (grads && grads->UL)
@@ -522,7 +525,7 @@ bf_status backward_fused(bf_plan *p, const void *g, const void *grad_u, void *gr
     const bfly::PassShape fs = bfly::fused_pass_shape(FP[j]);
     if (!store_all) {
       for (int d = 1; d < fs.K; ++d) aptr[td0[j] + d] = buf(seg0 + d - 1);
-      if ((st = run_forward(j, "_recompute")) != BF_OK) return st;
+      if ((st = run_forward(j, true)) != BF_OK) return st;
     }
     const bfly::PassShape as = bfly::fused_pass_shape(AP[i]);
     void *lvl[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};

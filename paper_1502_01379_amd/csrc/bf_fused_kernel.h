@@ -680,7 +680,8 @@ void k_fused_pass(FusedArgs a) {
   // ---- leaf blocks after the last level
   if constexpr (LO) pair_group(std::integral_constant<int, (LI ? 1 : 0) + K>{});
 
-  // ---- outputs at depth K
+  // ---- outputs at depth K (a.out == nullptr: only the per-depth copies are wanted)
+  if (!a.out) return;
   static_for<NS>([&](auto Q) {
     constexpr int q = Q;
     const int64_t slot = a.mode_si ? base + (lo << K) + q : base + ((int64_t)q << a.log_slo) + lo;
@@ -963,8 +964,8 @@ void k_fused_pass_x2(FusedArgs a) {
 
   if constexpr (LO) pair_group(std::integral_constant<int, (LI ? 1 : 0) + K>{});
 
-  // ---- outputs at depth K
-  if (!active) return;
+  // ---- outputs at depth K (a.out == nullptr: only the per-depth copies are wanted)
+  if (!active || !a.out) return;
   static_for<HS>([&](auto J) {
     constexpr int j = J;
     const int64_t q = qh + j;
