@@ -1,5 +1,6 @@
 // Host side of the C ABI declared in include/bf.h: argument checking, upload of
-// the factors, the order of the factor products, workspace and profiling.
+// the factors, the order of the factor products, the backward drivers (fused
+// passes with per-depth copies, or per-level kernels), workspace and profiling.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

@@ -2,8 +2,10 @@
 //
 // A pass applies K consecutive butterfly levels (plus, at the ends of the
 // product, the leaf blocks or the middle weights) to one tile of 2^K slots.
-// One wavefront owns COLS right-hand-side columns of the tile and keeps all of
-// its 2^K slots in registers for the whole pass.  Two lane geometries:
+// In k_fused_pass one wavefront owns COLS right-hand-side columns of the tile
+// and keeps all of its 2^K slots in registers for the whole pass; in
+// k_fused_pass_x2 (four-level passes) a pair of wavefronts shares the tile's
+// slots and swaps half of them through LDS once.  Two lane geometries:
 //
 //   COLS = 32 (v_mfma_*_32x32):  lane l -> column l % 32, half e = l / 32;
 //            the lane holds slot rows {4e..4e+3, 8+4e..11+4e} (8 complex).
@@ -17,9 +19,10 @@
 // The accumulator layout of one level holds, in each lane, exactly the rows
 // that the next level's B operand needs from that lane, so the interleaving of
 // slots between levels is register renaming: no LDS, no cross-lane traffic.
-// The A operands (the blocks) are packed on the host in per-lane order, 8 KB
-// per block, and read through L2 (every wavefront of a tile reads the same
-// blocks).
+// The A operands (the blocks) are packed in per-lane order, 8 KB per block
+// (4 KB per leaf pair in the 16-column geometry); every wavefront of a
+// workgroup works on the same tile, so the workgroup copies each stage of
+// blocks from L2 into LDS once (global -> LDS loads, one stage ahead).
 //
 // Precisions: FP32, and split BF16 / FP16 (x = hi + lo, three MFMA products
 // lo*hi + hi*lo + hi*hi with FP32 accumulation; FP16 also scales each block and
@@ -439,11 +442,11 @@ struct Geo<16> {
   __device__ static int pair(int e, int j) { return 2 * e + j; }
 };
 
-// Launch shape per pass depth.  Every pass fits two resident wavefronts per
-// SIMD (at most 256 registers).  Blocks are staged in LDS in groups of
-// kStageBlocks (double buffered, 2 x kStageBlocks x 8 KB); four-level passes
-// use half-level stages and four-wavefront workgroups so that two workgroups
-// share a CU and overlap each other's loads and stores.
+// Launch shape per pass depth of k_fused_pass.  Every pass fits at least two
+// resident wavefronts per SIMD (at most 256 registers).  Blocks are staged in
+// LDS in groups of kStageBlocks (double buffered, 2 x kStageBlocks x 8 KB);
+// four-level passes use half-level stages and four-wavefront workgroups so that
+// two workgroups share a CU and overlap each other's loads and stores.
 template <int COLS, int K>
 struct PassTraits {
   static constexpr int kWavesPerEU = 2;
