@@ -731,11 +731,14 @@ void k_fused_pass(FusedArgs a) {
 #ifndef BF_SPLIT_SWAP_KB
 #define BF_SPLIT_SWAP_KB 16
 #endif
+#ifndef BF_SPLIT_PB
+#define BF_SPLIT_PB 2
+#endif
 template <int K>
 struct SplitTraits {
   static constexpr int kHS = 1 << (K - 1);  // slots per wavefront
   static constexpr int kWB = kHS / 2;       // blocks per wavefront per level
-  static constexpr int kPB = kWB < 2 ? kWB : 2;  // blocks per wavefront per stage
+  static constexpr int kPB = kWB < BF_SPLIT_PB ? kWB : BF_SPLIT_PB;  // blocks per wavefront per stage
   static constexpr int kHB = 2 * kPB;            // blocks per stage
   static constexpr int kNPART = kWB / kPB;       // stages per block group
   static constexpr int kMaxPairs = BF_SPLIT_MAX_PAIRS;  // column chunks per workgroup
