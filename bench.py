@@ -270,8 +270,8 @@ def main():
             limiter = threadpool_limits(1)
         except Exception:
             limiter = None
-        sample = cols + [c for c in range(1, nrhs) if c not in cols][:max(0, 8 - len(cols))]
-        ncol = len(sample)  # about 10 s of one core at N = 2^20
+        sample = cols + [c for c in range(1, nrhs) if c not in cols][:max(0, 16 - len(cols))]
+        ncol = len(sample)  # about 10-15 s of one core at N = 2^20
         t2 = time.time()
         sub = oracle.bf_apply(f, g_host[:, sample].astype(np.complex128))
         dt = time.time() - t2
