@@ -44,6 +44,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 1 GiB device copy (reference for HBM byte counters)")
+    ap.add_argument("--shape", choices=sorted(SHAPES), default=None,
+                    help="time the apply on another workload shape instead of N=2^20")
+    ap.add_argument("--precision-override", default=None, choices=["f64", "f32", "bf16x3", "f16x3"],
+                    help="precision for --shape (default: the shape's own)")
     ap.add_argument("--construct", action="store_true",
                     help="time the construction from products of K F K instead of the apply")
     ap.add_argument("--backward", action="store_true",
@@ -162,6 +166,69 @@ def bench_construct(args):
     print(json.dumps(out), flush=True)
 
 
+SHAPES = {
+    # name: (radix, leaf, L, r, nrhs, precision, description)
+    "fourier1024": (2, 16, 6, 12, 1, "f64", "Fourier-shaped factorization, N=1024, leaf 16, r=12, 1 RHS"),
+    "fio65536": (2, 16, 12, 16, 64, "f32", "1D FIO-shaped factorization, N=65536, leaf 16, r=16, 64 RHS"),
+    "grt256": (4, 16, 6, 32, 128, "f32",
+               "2D GRT-shaped factorization, 256x256 points, quadtrees with 4x4 leaves, r=32, 128 RHS"),
+}
+
+
+def bench_shape(args):
+    """Apply timing on one of the other workload shapes (seeded synthetic factors of
+    that shape; the apply's cost does not depend on the values), with the roofline of
+    the whole apply from its algorithmic work: 2 N r (leaves) + L R r^2 P (butterflies)
+    + P r (middle) complex multiply-adds per RHS, and the factor bytes plus g and u."""
+    import torch
+    from bf_inputs import complex_gaussian, synthetic_factors
+    from paper_1502_01379_amd import BFHandle
+    R, leaf, L, r, nrhs, prec, desc = SHAPES[args.shape]
+    if args.precision_override:
+        prec = args.precision_override
+    P = R ** L
+    N = leaf * P
+    f = synthetic_factors(R, leaf, L, r, seed=50)
+    cdt = np.complex128 if prec == "f64" else np.complex64
+    g = torch.from_numpy(complex_gaussian((N, nrhs), 51, dtype=cdt)).to("cuda")
+    u = torch.empty_like(g)
+    h = BFHandle(f, prec)
+    for _ in range(args.warmup):
+        h.apply(g, out=u)
+    torch.cuda.synchronize()
+    # timed without per-launch events (they cost microseconds on the small shapes),
+    # then once more with them for the per-kernel split
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        h.apply(g, out=u)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    h.set_profiling(True)
+    h.kernel_times(reset=True)
+    for _ in range(args.steps):
+        h.apply(g, out=u)
+    torch.cuda.synchronize()
+    kt = h.kernel_times(reset=True)
+    h.set_profiling(False)
+    cmac = 2 * N * r + L * R * r * r * P + P * r
+    flops = 8.0 * cmac * nrhs
+    cb = 16 if prec == "f64" else 8
+    bytes_ = (2 * N * r + L * P * R * r * r) * cb + 2 * N * nrhs * cb
+    peak = {"f64": 78.6, "f32": 157.3, "bf16x3": 2516.6 / 3, "f16x3": 2516.6 / 3}[prec]
+    t_roof = max(flops / (peak * 1e12), bytes_ / (HBM_PEAK_GBS * 1e9)) * 1e3
+    out = {"metric": "BF apply RHS·N/s", "value": nrhs * N / (ms * 1e-3), "unit": "RHS·N/s",
+           "ms_per_step": ms, "precision": prec, "data": "synthetic",
+           "config": {"workload": desc, "N": N, "radix": R, "leaf": leaf, "L": L, "r": r, "nrhs": nrhs},
+           "kernel_path": "fused MFMA passes" if h.path == 1 else "per-level kernels",
+           "whole_apply_roofline": {"ms": t_roof, "bound": "compute" if flops / (peak * 1e12) >=
+                                    bytes_ / (HBM_PEAK_GBS * 1e9) else "hbm",
+                                    "frac": t_roof / ms, "flops": flops, "bytes": bytes_},
+           "kernels_ms_per_step": {k: v[0] / args.steps for k, v in kt.items()}}
+    print(json.dumps(out), flush=True)
+
+
 def pass_work(name, L, r, leaf, nrhs, K, has_leaf, has_middle):
     """Algorithmic flops and compulsory HBM bytes of one fused-pass launch.
 
@@ -212,6 +279,9 @@ def main():
         return
     if args.construct:
         bench_construct(args)
+        return
+    if args.shape:
+        bench_shape(args)
         return
     import torch
 
