@@ -48,6 +48,8 @@ def parse():
                     help="time the apply on another workload shape instead of N=2^20")
     ap.add_argument("--precision-override", default=None, choices=["f64", "f32", "bf16x3", "f16x3"],
                     help="precision for --shape (default: the shape's own)")
+    ap.add_argument("--graph", action="store_true",
+                    help="with --shape: also time the apply replayed from a HIP graph")
     ap.add_argument("--construct", action="store_true",
                     help="time the construction from products of K F K instead of the apply")
     ap.add_argument("--backward", action="store_true",
@@ -205,6 +207,20 @@ def bench_shape(args):
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / args.steps
+    graph_ms = None
+    if args.graph:
+        # the same apply recorded once in a HIP graph and replayed (launch-bound shapes)
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            h.apply(g, out=u)
+        graph.replay()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(args.steps):
+            graph.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        graph_ms = e0.elapsed_time(e1) / args.steps
     h.set_profiling(True)
     h.kernel_times(reset=True)
     for _ in range(args.steps):
@@ -226,6 +242,8 @@ def bench_shape(args):
                                     bytes_ / (HBM_PEAK_GBS * 1e9) else "hbm",
                                     "frac": t_roof / ms, "flops": flops, "bytes": bytes_},
            "kernels_ms_per_step": {k: v[0] / args.steps for k, v in kt.items()}}
+    if graph_ms is not None:
+        out["hip_graph_ms_per_step"] = graph_ms
     print(json.dumps(out), flush=True)
 
 
