@@ -139,8 +139,9 @@ bf_status bf_apply_adjoint(bf_handle h, const void *w, void *v, int64_t nrhs, in
  * boundaries on the fused path, every fourth level otherwise) and the others
  * are recomputed inside the call; BF_BWD_STORE_ALL keeps all 2h + 2 of them
  * (more workspace, less work).  Both modes give identical results.  On the fused
- * path the backward pass computes in FP32 for every precision; its first call
- * on a handle also packs FP32 copies of the blocks (device memory owned by the
+ * path the backward passes compute in split BF16 for BF_PREC_SPLIT_BF16 handles
+ * and in FP32 otherwise (gradient sums in FP32); its first call on a handle also
+ * packs copies of the blocks in that precision (device memory owned by the
  * handle, about the size of the packed factors).  The workspace
  * (owned by the handle, grown on demand) is about (2h + 8) activation arrays
  * with BF_BWD_STORE_ALL and 15 without, each P r nrhs complex values.

@@ -45,7 +45,19 @@ __device__ __forceinline__ float block_value(const float2 *__restrict__ Fb, int6
 // place in the level-by-level slot order is fixed by the pass's slot mode (the
 // same map the pass uses for its per-depth copies); the level's butterfly index
 // follows from the slot pattern of that level (strided or contiguous input).
-__global__ void k_pack_pass(PackPassArgs a, float *__restrict__ out) {
+// RNE split of an FP32 value into BF16 hi + lo, as bit patterns
+__device__ __forceinline__ void split_bf16(float v, uint16_t &hi, uint16_t &lo) {
+  const __bf16 h = (__bf16)v;
+  const __bf16 l = (__bf16)(v - (float)h);
+  hi = __builtin_bit_cast(uint16_t, h);
+  lo = __builtin_bit_cast(uint16_t, l);
+}
+
+// split = 0: FP32 layout, value 16 T + s of lane (i, e) at float (s / 4 ... ) as the
+// 16-column FP32 product reads it; split = 1: BF16 hi / lo layout of the split
+// product (piece w = 2 T + part holds this lane's 8 values j: input row 16 (j / 4)
+// + 4 e + j % 4; hi in pieces 0 .. 3, lo in pieces 4 .. 7)
+__global__ void k_pack_pass(PackPassArgs a, float *__restrict__ out, int split) {
   const int64_t NB = int64_t(1) << (a.K - 1);
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (t >= (int64_t)a.K * a.ntiles * NB * 2048) return;
@@ -66,9 +78,21 @@ __global__ void k_pack_pass(PackPassArgs a, float *__restrict__ out) {
   const PackDepth &pd = a.dep[d];
   const int64_t blo = int64_t(1) << pd.log_blo;
   const int64_t b = pd.contig ? (slot >> 1) : (((slot >> (pd.log_blo + 1)) << pd.log_blo) | (slot & (blo - 1)));
+  const int i = lane & 15, e = lane >> 4;
+  if (split) {
+    const int w = f >> 3, j = f & 7;
+    const int T = w >> 1, part = w & 1;
+    const float v = block_value(static_cast<const float2 *>(pd.Fb), b / blo, b % blo, blo, pd.tconj,
+                                16 * T + i, 16 * (j >> 2) + 4 * e + (j & 3), part);
+    uint16_t hi, lo16;
+    split_bf16(v, hi, lo16);
+    uint16_t *o16 = reinterpret_cast<uint16_t *>(out) + bi * 4096;
+    o16[(w * 64 + lane) * 8 + j] = hi;
+    o16[((4 + w) * 64 + lane) * 8 + j] = lo16;
+    return;
+  }
   const int T = f >> 4, sidx = f & 15;
   const int part = sidx >> 3, cp = (sidx >> 2) & 1, rho = sidx & 3;
-  const int i = lane & 15, e = lane >> 4;
   const float v = block_value(static_cast<const float2 *>(pd.Fb), b / blo, b % blo, blo, pd.tconj,
                               16 * T + i, 16 * cp + 4 * e + rho, part);
   out[bi * 2048 + ((f >> 2) * 64 + lane) * 4 + (f & 3)] = v;
@@ -78,20 +102,32 @@ __global__ void k_pack_pass(PackPassArgs a, float *__restrict__ out) {
 // blocks: in  M_c[a][p] = conj(W[j][p][a]),  out  M_c[p][a] = W[j][p][a];
 // value j of lane i + 16 e is [Re M_c, -Im M_c][i][(j / 4, 4 e + j % 4)].
 __global__ void k_pack_leaf16(const float2 *__restrict__ W, float *__restrict__ out, int64_t npairs,
-                              int K, int in) {
+                              int K, int in, int split) {
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (t >= npairs * 1024) return;
   const int64_t bi = t >> 10;
   const int w = (int)(t & 1023);
-  const int c = w >> 9, pc = (w >> 8) & 1, lane = (w >> 2) & 63, jj = w & 3;
-  const int jv = pc * 4 + jj;  // value index 0..7
+  // FP32: 2 pieces of 4 floats per slot; split: this thread makes value jv's hi and lo
+  const int c = w >> 9;
+  const int lane = split ? (w >> 3) & 63 : (w >> 2) & 63;
+  const int pc = split ? 0 : (w >> 8) & 1, jj = split ? 0 : w & 3;
+  const int jv = split ? (w & 7) : pc * 4 + jj;  // value index 0..7
   const int i = lane & 15, e = lane >> 4;
   const int k = 4 * e + (jv & 3);
   const int64_t tile = bi >> (K - 1), qq = bi & ((int64_t(1) << (K - 1)) - 1);
   const int64_t leaf = (tile << K) + 2 * qq + c;
   float2 m = in ? W[(leaf * kR + k) * kR + i] : W[(leaf * kR + i) * kR + k];
   if (in) m.y = -m.y;
-  out[bi * 1024 + ((c * 2 + pc) * 64 + lane) * 4 + jj] = (jv >> 2) == 0 ? m.x : -m.y;
+  const float v = (jv >> 2) == 0 ? m.x : -m.y;
+  if (split) {
+    uint16_t hi, lo;
+    split_bf16(v, hi, lo);
+    uint16_t *o16 = reinterpret_cast<uint16_t *>(out) + bi * 2048;
+    o16[((c * 2 + 0) * 64 + lane) * 8 + jv] = hi;
+    o16[((c * 2 + 1) * 64 + lane) * 8 + jv] = lo;
+    return;
+  }
+  out[bi * 1024 + ((c * 2 + pc) * 64 + lane) * 4 + jj] = v;
 }
 
 constexpr int kRowPad = 272;  // bytes per column of a staged 32-row chunk (256 + 16)
@@ -310,19 +346,20 @@ hipError_t launch_grad_leaf_mfma(const bf_plan *p, const void *user, int64_t ld,
   return hipGetLastError();
 }
 
-hipError_t launch_pack_pass(const PackPassArgs &a, void *out, hipStream_t s) {
+hipError_t launch_pack_pass(const PackPassArgs &a, void *out, bool split, hipStream_t s) {
   const int bs = 256;
   const int64_t total = (int64_t)a.K * a.ntiles * (int64_t(1) << (a.K - 1)) * 2048;
-  hipLaunchKernelGGL(k_pack_pass, dim3((unsigned)((total + bs - 1) / bs)), dim3(bs), 0, s, a, (float *)out);
+  hipLaunchKernelGGL(k_pack_pass, dim3((unsigned)((total + bs - 1) / bs)), dim3(bs), 0, s, a, (float *)out,
+                     split ? 1 : 0);
   return hipGetLastError();
 }
 
 hipError_t launch_pack_leaf16(const void *canon_leaf, void *out, int64_t npairs, int K, bool in,
-                              hipStream_t s) {
+                              bool split, hipStream_t s) {
   const int bs = 256;
   const int64_t total = npairs * 1024;
   hipLaunchKernelGGL(k_pack_leaf16, dim3((unsigned)((total + bs - 1) / bs)), dim3(bs), 0, s,
-                     (const float2 *)canon_leaf, (float *)out, npairs, K, in ? 1 : 0);
+                     (const float2 *)canon_leaf, (float *)out, npairs, K, in ? 1 : 0, split ? 1 : 0);
   return hipGetLastError();
 }
 

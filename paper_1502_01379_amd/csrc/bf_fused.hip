@@ -492,12 +492,13 @@ hipError_t fused_run(bf_plan *p, bool adjoint, const void *g, void *u, int64_t n
   return hipSuccess;
 }
 
-// FP32 passes of the backward pass: the pass split of the apply, 16-column
-// geometry, blocks packed on the device from the canonical factors the handle
-// holds.  The forward list has no leaf-out blocks: the backward pass needs the
+// Passes of the backward pass: the pass split of the apply, 16-column geometry,
+// blocks packed on the device from the canonical factors the handle holds (split
+// BF16 for split-BF16 handles, FP32 for the others).  The forward list has no leaf-out blocks: the backward pass needs the
 // state before U^L, not u.
 bf_status fused_build_backward(bf_plan *p, hipStream_t s) {
   const int L = p->L, h = p->h;
+  p->bwd_bf16 = p->prec == BF_PREC_SPLIT_BF16;
   const std::vector<int> ks = split_levels(h, 4);
   // middle weights (S, S^T) as the apply passes hold them
   const float *Sm[2] = {nullptr, nullptr};
@@ -559,13 +560,13 @@ bf_status fused_build_backward(bf_plan *p, hipStream_t s) {
         bf_status st = alloc(fp, (size_t)(K * fp->ntiles * NB) * kBlockBytes, &d);
         if (st != BF_OK) return st;
         fp->fac = d;
-        hipError_t e = launch_pack_pass(pa, d, s);
+        hipError_t e = launch_pack_pass(pa, d, p->bwd_bf16, s);
         if (e == hipSuccess && (fp->in_kind == kInUser || fp->out_kind == kOutUser)) {
           const bool in = fp->in_kind == kInUser;
           const LevelOp &lop = in ? ops.front() : ops.back();
           if ((st = alloc(fp, (size_t)(fp->ntiles * NB) * (kBlockBytes / 2), &d)) != BF_OK) return st;
           fp->leaf = d;
-          e = launch_pack_leaf16(lop.mat, d, fp->ntiles * NB, K, in, s);
+          e = launch_pack_leaf16(lop.mat, d, fp->ntiles * NB, K, in, p->bwd_bf16, s);
         }
         if (e != hipSuccess) {
           p->err = std::string("backward pack: ") + hipGetErrorString(e);
@@ -591,6 +592,7 @@ hipError_t fused_run_pass(const bf_plan *p, const FusedPass *fp, const void *in,
   if (lvl)
     for (int d = 0; d <= fp->K; ++d) a.lvl[d] = lvl[d];
   const bool li = fp->in_kind == kInUser, lo = fp->out_kind == kOutUser;
+  if (p->bwd_bf16) return launch_prec<kBF16>(a, fp->cols, fp->K, li, lo, fp->split, s);
   return launch_prec<kF32>(a, fp->cols, fp->K, li, lo, fp->split, s);
 }
 

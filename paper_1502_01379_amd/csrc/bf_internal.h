@@ -81,10 +81,12 @@ struct bf_plan {
   std::vector<bfly::LevelOp> fwd_ops, adj_ops;
   // fused path
   std::vector<bfly::FusedPass *> fwd_passes, adj_passes;
-  // FP32 fused passes of the backward pass (same pass split as the apply; the
-  // forward list stops before the leaf-out blocks), built on first use
+  // fused passes of the backward pass (same pass split as the apply; the forward
+  // list stops before the leaf-out blocks), built on first use: split BF16 for
+  // split-BF16 handles, FP32 otherwise
   std::vector<bfly::FusedPass *> bwd_fwd, bwd_adj;
   bool bwd_ready = false;
+  bool bwd_bf16 = false;
   // middle weights, FP32 or FP64 by precision: S[i][j][k] and its transpose
   void *S = nullptr, *ST = nullptr;
 
@@ -122,9 +124,10 @@ hipError_t launch_level_mfma(const bf_plan *p, const LevelOp &op, const void *in
                              int64_t nrhs, hipStream_t s);
 
 // Backward helpers for fused-path handles (bf_bwd.hip)
-hipError_t launch_pack_pass(const PackPassArgs &a, void *out, hipStream_t s);
+// split = true: BF16 hi / lo blocks for the split-BF16 passes, else FP32 blocks
+hipError_t launch_pack_pass(const PackPassArgs &a, void *out, bool split, hipStream_t s);
 hipError_t launch_pack_leaf16(const void *canon_leaf, void *out, int64_t npairs, int K, bool in,
-                              hipStream_t s);
+                              bool split, hipStream_t s);
 hipError_t launch_grad_level_mfma(const bf_plan *p, const LevelOp &op, const void *X, const void *Y,
                                   void *grad, int64_t nrhs, hipStream_t s);
 // middle weights, 16-column activation chunks, r = 16 (FP32)

@@ -25,7 +25,7 @@ def _loss(op, g, y):
     return (u - y).abs().pow(2).sum()
 
 
-@pytest.mark.parametrize("prec,tol", [("f64", 1e-10), ("f32", 1e-5), ("bf16x3", 1e-5)])
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-10), ("f32", 1e-5), ("bf16x3", 1e-4)])
 def test_autograd_matches_oracle_gradient(dev, prec, tol):
     # L = ||K_BF g - y||^2 with y = K g + noise; every parameter gradient and grad g
     from paper_1502_01379_amd import BFOperator
@@ -51,7 +51,7 @@ def test_autograd_matches_oracle_gradient(dev, prec, tol):
     pairs = [(p["VL"], ref["VL"]), (p["UL"], ref["UL"]), (p["S"], ref["S"])]
     pairs += list(zip(p["H"], ref["H"])) + list(zip(p["G"], ref["G"]))
     for t, r in pairs:
-        assert oracle.rel_err(t.grad.cpu().numpy(), r) < 10 * tol
+        assert oracle.rel_err(t.grad.cpu().numpy(), r) < (10 * tol if prec != "bf16x3" else tol)
 
 
 def test_autograd_finite_differences(dev):

@@ -156,9 +156,9 @@ def test_backward_on_fused_handle(dev, fio4096, prec):
     ref = oracle.bf_grad(f, g, gu)
     h = _handle(f, prec)
     grad_g, grads = h.backward(_dev(g, dev), _dev(gu, dev))
-    assert oracle.rel_err(grad_g.cpu().numpy(), ref["g"]) < 1e-5
-    assert oracle.rel_err(grads["H"][0].cpu().numpy(), ref["H"][0]) < 1e-4
-    assert oracle.rel_err(grads["S"].cpu().numpy(), ref["S"]) < 1e-4
+    assert oracle.rel_err(grad_g.cpu().numpy(), ref["g"]) < TOL[prec]
+    assert oracle.rel_err(grads["H"][0].cpu().numpy(), ref["H"][0]) < max(TOL[prec], 1e-5)
+    assert oracle.rel_err(grads["S"].cpu().numpy(), ref["S"]) < max(TOL[prec], 1e-5)
 
 
 def _flat(d):
@@ -169,8 +169,9 @@ def _flat(d):
 @pytest.mark.parametrize("prec", ["f32", "bf16x3", "f16x3"])
 def test_fused_backward_tree_depths(dev, L, prec):
     # backward passes of one to four levels, one or two passes per side; every
-    # gradient against the oracle, and recomputing the states inside the passes
-    # gives the same bits as keeping them
+    # gradient against the oracle (split-BF16 handles run the passes in split BF16,
+    # the others in FP32), and recomputing the states inside the passes gives the
+    # same bits as keeping them
     from paper_1502_01379_amd import BF_BWD_STORE_ALL
     f = synthetic_factors(2, 16, L, 16, seed=80 + L)
     N = 16 * 2 ** L
@@ -180,9 +181,10 @@ def test_fused_backward_tree_depths(dev, L, prec):
     ref = oracle.bf_grad(f, g, gu)
     h = _handle(f, prec)
     grad_g, grads = h.backward(_dev(g, dev), _dev(gu, dev))
-    assert oracle.rel_err(grad_g.cpu().numpy(), ref["g"]) < 1e-5
+    tol = TOL["bf16x3"] if prec == "bf16x3" else 1e-5
+    assert oracle.rel_err(grad_g.cpu().numpy(), ref["g"]) < tol
     for a, b in zip(_flat(grads), _flat(ref)):
-        assert oracle.rel_err(a.cpu().numpy(), b) < 1e-5
+        assert oracle.rel_err(a.cpu().numpy(), b) < tol
     grad_g2, grads2 = h.backward(_dev(g, dev), _dev(gu, dev), flags=BF_BWD_STORE_ALL)
     assert torch.equal(grad_g, grad_g2)
     for a, b in zip(_flat(grads), _flat(grads2)):
