@@ -7,18 +7,19 @@ layout (see include/bf.h) and applies it to complex torch tensors on the GPU;
 `bf_apply_autograd` and `BFOperator` expose the hand-written adjoint and
 backward kernels to torch.autograd.  Precisions: "f64", "f32", "bf16x3"
 (split BF16, three MFMA products, FP32 accumulation) and "f16x3".
-`construct_from_products` builds a factorization of an operator given only
-through products with K and K^* (Alg. 2.1, first case of Sec. 3.1).
+`construct_from_entries` and `construct_from_products` build a factorization on
+the host in FP64 from entries of K (Alg. 2.2) or from products with K and K^*
+(Alg. 2.1), the two cases of Sec. 3.1.
 """
 from __future__ import annotations
 
 from .binding import (BF_BWD_RECOMPUTE, BF_BWD_STORE_ALL, BFError, BFHandle, PRECISIONS,  # noqa: F401
                       load_library)
 
-from .construct import construct_from_products  # noqa: F401,E402
+from .construct import construct_from_entries, construct_from_products  # noqa: F401,E402
 
 __all__ = ["BFHandle", "BFError", "BFOperator", "bf_apply_autograd", "load_library", "PRECISIONS",
-           "BF_BWD_RECOMPUTE", "BF_BWD_STORE_ALL", "construct_from_products"]
+           "BF_BWD_RECOMPUTE", "BF_BWD_STORE_ALL", "construct_from_entries", "construct_from_products"]
 
 _FACTOR_KEYS = ("VL", "UL", "S")
 

@@ -1,12 +1,19 @@
-"""Butterfly factorization of an operator known only through products with K and K^*.
+"""Construction of the butterfly factorization (Sec. 3) on the host in FP64, as the
+construction's stability needs; the result is the canonical factor set that
+``bf_create_from_factors`` (``BFHandle``) takes.
 
-This is the first case of Sec. 3.1: the middle level is factorized by the
-randomized SVD of Sec. 2.1 (Algorithm 2.1) from two products with block-diagonal
-Gaussian matrices, and the factors of the middle level are then factorized
-recursively as in Sec. 3.2.  The products are a caller-supplied black box on the
-GPU (for instance this library's ``bf_apply`` composed with an FFT, Sec. 4
-Example 3); the linear algebra runs on the host in FP64, as the construction's
-stability needs.
+Two routes, the two cases of Sec. 3.1:
+
+* ``construct_from_entries``: entries of K are available (a callable returning
+  submatrices); every middle-level block is factorized by randomized sampling
+  (Algorithm 2.2).
+* ``construct_from_products``: only products with K and K^* are available (for
+  instance this library's ``bf_apply`` composed with an FFT, Sec. 4 Example 3, on
+  the GPU); the middle level comes from the randomized SVD (Algorithm 2.1) of two
+  products with block-diagonal Gaussian matrices.
+
+Both then factorize the middle level recursively (Sec. 3.2.1, 3.2.2), batched
+over all nodes of a level.
 
     f = construct_from_products(N, radix, leaf, r, apply, apply_adjoint)
     h = BFHandle(f, "bf16x3")
@@ -117,6 +124,87 @@ def _recursive(Wb, R, r, levels):
     return blocks, cur[:, 0]
 
 
+def _pick(rng, dim, count, taken):
+    """`count` random indices of range(dim) outside `taken` (all of them if fewer remain)."""
+    free = np.setdiff1d(np.arange(dim), taken, assume_unique=False)
+    if free.size <= count:
+        return free
+    return np.sort(rng.choice(free, size=count, replace=False))
+
+
+def _sampled_block(entries, b, r, rng, q=3, iters=3):
+    """Rank-r SVD of one b x b block Z from O(r) of its rows and columns (Alg. 2.2).
+
+    entries(I, J) returns Z[I][:, J].  Steps 2-3 alternate `iters` times: a
+    pivoted QR of the sampled rows (plus the important rows so far) picks the r
+    important columns, a pivoted QR of the conjugate transpose of the sampled
+    columns (the pivoted LQ) picks the r important rows.  Step 5 fits the middle
+    matrix on the important indices plus r q fresh ones in least squares.
+    """
+    pcol = np.zeros(0, dtype=np.int64)
+    prow = np.zeros(0, dtype=np.int64)
+    for _ in range(iters):
+        I = np.union1d(_pick(rng, b, r * q, prow), prow)
+        piv = sla.qr(entries(I, np.arange(b)), mode="r", pivoting=True)[1]
+        pcol = np.sort(piv[:r])
+        J = np.union1d(_pick(rng, b, r * q, pcol), pcol)
+        piv = sla.qr(entries(np.arange(b), J).conj().T, mode="r", pivoting=True)[1]
+        prow = np.sort(piv[:r])
+    Qc = sla.qr(entries(np.arange(b), pcol), mode="economic", pivoting=True)[0][:, :r]
+    Qr = sla.qr(entries(prow, np.arange(b)).conj().T, mode="economic", pivoting=True)[0][:, :r]
+    I = np.union1d(prow, _pick(rng, b, r * q, prow))
+    J = np.union1d(pcol, _pick(rng, b, r * q, pcol))
+    M = (np.linalg.pinv(Qc[I], rcond=1e-14) @ entries(I, J)
+         @ np.linalg.pinv(Qr[J].conj().T, rcond=1e-14))
+    Um, sm, Vmh = _svd_rank(M, r)
+    return Qc @ Um, sm, Vmh @ Qr.conj().T
+
+
+def _first_form(U0, s, V0h, drop_rel):
+    keep = (s > 0) & (s > drop_rel * (s[0] if s.size else 0.0))
+    sk = np.where(keep, s, 0.0)
+    return U0 * sk, (V0h * sk[:, None]).conj().T, np.where(keep, 1.0 / np.where(keep, s, 1.0), 0.0)
+
+
+def _from_middle(N, R, leaf, L, r, Uh, Vh, S):
+    lv = L - L // 2
+    Gb, UL = _recursive(Uh, R, r, lv)
+    Hb, VL = _recursive(Vh, R, r, lv)
+    return {"radix": R, "leaf": int(leaf), "L": L, "r": int(r),
+            "VL": VL, "UL": UL, "S": S, "H": Hb, "G": Gb}
+
+
+def construct_from_entries(N, radix, leaf, r, entries, q=3, iters=3, seed=0, drop_rel=1e-14):
+    """Canonical factors of K from its entries (the second case of Sec. 3.1).
+
+    entries(rows, cols) returns the dense submatrix K[rows][:, cols] (FP64 complex)
+    for index arrays in tree order.  Every middle-level block gets its rank-r SVD
+    by randomized sampling (Alg. 2.2), with its own random stream, so the result
+    does not depend on the order the blocks are processed in; the blocks are
+    spread over threads, and the recursion of Sec. 3.2 is batched over every node.
+    """
+    R = int(radix)
+    L = _depth(N, leaf, R)
+    m = R ** (L // 2)
+    b = N // m
+    Uh = np.zeros((m, m, b, r), dtype=np.complex128)
+    Vh = np.zeros((m, m, b, r), dtype=np.complex128)
+    S = np.zeros((m, m, r))
+
+    def row(i):
+        for j in range(m):
+            rng = np.random.default_rng([seed, i, j])
+            rows, cols = i * b, j * b
+            U0, s, V0h = _sampled_block(lambda I, J: entries(rows + I, cols + J), b, r, rng, q, iters)
+            Uh[i, j], Vh[j, i], S[i, j] = _first_form(U0, s, V0h, drop_rel)
+
+    # small blocks spend their time in the interpreter, where threads only contend
+    nt = min(_threads(), m) if b >= 256 else 1
+    with _one_blas_thread(), ThreadPoolExecutor(nt) as ex:
+        list(ex.map(row, range(m)))
+    return _from_middle(N, R, leaf, L, r, Uh, Vh, S)
+
+
 def construct_from_products(N, radix, leaf, r, apply, apply_adjoint, p=5, seed=0, drop_rel=1e-14,
                             device="cuda"):
     """Canonical factors of K (see the module docstring); the test matrices are
@@ -155,19 +243,10 @@ def construct_from_products(N, radix, leaf, r, apply, apply_adjoint, p=5, seed=0
         for j in range(m):
             U0, s, V0h = _middle_block(KC[i * b:(i + 1) * b, j * k:(j + 1) * k],
                                        KR[j * b:(j + 1) * b, i * k:(i + 1) * k], Cb[j], r)
-            keep = (s > 0) & (s > drop_rel * s[0])
-            sk = np.where(keep, s, 0.0)
-            Uh[i, j] = U0 * sk
-            Vh[j, i] = (V0h * sk[:, None]).conj().T
-            S[i, j] = np.where(keep, 1.0 / np.where(keep, s, 1.0), 0.0)
+            Uh[i, j], Vh[j, i], S[i, j] = _first_form(U0, s, V0h, drop_rel)
 
     with _one_blas_thread(), ThreadPoolExecutor(min(_threads(), m)) as ex:
         list(ex.map(row, range(m)))
-
-    lv = L - h
-    Gb, UL = _recursive(Uh, R, r, lv)
-    Hb, VL = _recursive(Vh, R, r, lv)
     # the node of depth t below middle node i with child path c is R^(t+1) i + path:
     # _recursive already orders its outputs that way
-    return {"radix": R, "leaf": int(leaf), "L": L, "r": int(r),
-            "VL": VL, "UL": UL, "S": S, "H": Hb, "G": Gb}
+    return _from_middle(N, R, leaf, L, r, Uh, Vh, S)

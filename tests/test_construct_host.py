@@ -47,3 +47,58 @@ def test_fourier_through_fft_matches_oracle_accuracy():
     fo = oracle.construct_factors_matvec(N, 2, 16, r, lambda X: K @ X, lambda X: K.conj().T @ X, seed=9)
     e_ora = oracle.rel_err(oracle.bf_apply(fo, g), K @ g)
     assert e_lib < 3 * e_ora + 1e-12
+
+
+def test_entries_full_rank_is_exact():
+    """Rank r equal to the middle block size: the sampled SVD is exact (Alg. 2.2)."""
+    from paper_1502_01379_amd.construct import construct_from_entries
+    kern = kernels.fio(64)
+    K = kernels.dense_matrix(kern)
+    f = construct_from_entries(64, 2, 4, 16, kern.entries, seed=3)
+    g = complex_gaussian((64, 3), 1)
+    assert oracle.rel_err(oracle.bf_apply(f, g), K @ g) < 1e-12
+
+
+def test_entries_recovers_a_low_rank_kernel():
+    """Every block of A B^T has rank 5: the sampled factorization reproduces it."""
+    from paper_1502_01379_amd.construct import construct_from_entries
+    N = 256
+    rng = np.random.default_rng(4)
+    A = rng.standard_normal((N, 5)) + 1j * rng.standard_normal((N, 5))
+    B = rng.standard_normal((N, 5)) + 1j * rng.standard_normal((N, 5))
+    kern = kernels.LowRankKernel(A, B)
+    f = construct_from_entries(N, 2, 4, 7, kern.entries, seed=2)
+    assert oracle.rel_err(oracle.bf_apply(f, np.eye(N)), A @ B.T) < 1e-11
+
+
+@pytest.mark.parametrize("radix,leaf,L,r0", [(2, 4, 6, 3), (4, 2, 4, 2)])
+def test_entries_recovers_an_exact_butterfly(radix, leaf, L, r0):
+    from paper_1502_01379_amd.construct import construct_from_entries
+    fs = synthetic_factors(radix, leaf, L, r0, seed=5)
+    N = leaf * radix ** L
+    K = oracle.bf_apply(fs, np.eye(N, dtype=complex))
+    f = construct_from_entries(N, radix, leaf, r0 + 2, lambda I, J: K[np.ix_(I, J)], seed=6)
+    assert oracle.rel_err(oracle.bf_apply(f, np.eye(N)), K) < 1e-11
+
+
+def test_entries_fourier_matches_oracle_accuracy():
+    """Same accuracy as the oracle's sampling construction on the Fourier kernel."""
+    from paper_1502_01379_amd.construct import construct_from_entries
+    N, r = 1024, 24
+    kern = kernels.fourier(N)
+    K = kernels.dense_matrix(kern)
+    g = complex_gaussian((N, 3), 8)
+    f = construct_from_entries(N, 2, 16, r, kern.entries, seed=9)
+    e_lib = oracle.rel_err(oracle.bf_apply(f, g), K @ g)
+    fo = oracle.construct_factors(kern, leaf=16, r=r, method="sampling", seed=9)
+    e_ora = oracle.rel_err(oracle.bf_apply(fo, g), K @ g)
+    assert e_lib < 3 * e_ora + 1e-12
+
+
+def test_entries_seed_fixes_the_result():
+    from paper_1502_01379_amd.construct import construct_from_entries
+    kern = kernels.fio(256)
+    a = construct_from_entries(256, 2, 4, 8, kern.entries, seed=1)
+    b = construct_from_entries(256, 2, 4, 8, kern.entries, seed=1)
+    for key in ("VL", "UL", "S"):
+        assert np.array_equal(a[key], b[key])
