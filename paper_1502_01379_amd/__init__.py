@@ -9,17 +9,22 @@ backward kernels to torch.autograd.  Precisions: "f64", "f32", "bf16x3"
 (split BF16, three MFMA products, FP32 accumulation) and "f16x3".
 `construct_from_entries` and `construct_from_products` build a factorization on
 the host in FP64 from entries of K (Alg. 2.2) or from products with K and K^*
-(Alg. 2.1), the two cases of Sec. 3.1.
+(Alg. 2.1), the two cases of Sec. 3.1.  The batched FP64 GPU primitives of the
+construction (`kernel_entries`, `batched_svd`, `batched_qr`,
+`batched_column_pivots`) are exposed; `construct_on_device`, their driver for the
+whole entry route, is switched off for now (it raises BFError).
 """
 from __future__ import annotations
 
 from .binding import (BF_BWD_RECOMPUTE, BF_BWD_STORE_ALL, BFError, BFHandle, PRECISIONS,  # noqa: F401
-                      load_library)
+                      batched_column_pivots, batched_qr, batched_svd, construct_on_device,
+                      kernel_entries, load_library)
 
 from .construct import construct_from_entries, construct_from_products  # noqa: F401,E402
 
 __all__ = ["BFHandle", "BFError", "BFOperator", "bf_apply_autograd", "load_library", "PRECISIONS",
-           "BF_BWD_RECOMPUTE", "BF_BWD_STORE_ALL", "construct_from_entries", "construct_from_products"]
+           "BF_BWD_RECOMPUTE", "BF_BWD_STORE_ALL", "construct_from_entries", "construct_from_products",
+           "construct_on_device", "kernel_entries", "batched_svd", "batched_qr", "batched_column_pivots"]
 
 _FACTOR_KEYS = ("VL", "UL", "S")
 

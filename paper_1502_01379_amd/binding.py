@@ -23,7 +23,11 @@ BF_BWD_RECOMPUTE = 0
 BF_BWD_STORE_ALL = 1
 
 EXPORTED = ["bf_create_from_factors", "bf_apply", "bf_apply_adjoint", "bf_backward", "bf_destroy",
-            "bf_last_error", "bf_query", "bf_set_profiling", "bf_kernel_times"]
+            "bf_last_error", "bf_query", "bf_set_profiling", "bf_kernel_times",
+            # include/bf_construct.h
+            "bf_kernel_entries", "bf_batched_svd", "bf_batched_qr", "bf_batched_column_pivots",
+            "bf_construct_from_kernel"]
+KERNELS = {"fourier": 0, "fio": 1}
 
 
 class BFShape(ctypes.Structure):
@@ -43,6 +47,11 @@ class BFFactorGrads(ctypes.Structure):
     _fields_ = [("VL", ctypes.c_void_p), ("H", ctypes.POINTER(ctypes.c_void_p)),
                 ("S", ctypes.c_void_p), ("G", ctypes.POINTER(ctypes.c_void_p)),
                 ("UL", ctypes.c_void_p)]
+
+
+class BFFactorsOut(ctypes.Structure):
+    _fields_ = [("VL", _PD), ("H", ctypes.POINTER(_PD)), ("S", _PD),
+                ("G", ctypes.POINTER(_PD)), ("UL", _PD)]
 
 
 class BFError(RuntimeError):
@@ -84,6 +93,17 @@ def load_library(path=LIB_PATH):
     lib.bf_kernel_times.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64),
                                     i32, ctypes.POINTER(i32), i32]
     lib.bf_kernel_times.restype = ctypes.c_int
+    lib.bf_kernel_entries.argtypes = [i32, i64, vp, i64, vp, i64, vp, i64, vp]
+    lib.bf_kernel_entries.restype = ctypes.c_int
+    lib.bf_batched_svd.argtypes = [vp, i64, i32, i32, vp, vp, vp, vp]
+    lib.bf_batched_svd.restype = ctypes.c_int
+    lib.bf_batched_qr.argtypes = [vp, i64, i64, i32, vp, vp]
+    lib.bf_batched_qr.restype = ctypes.c_int
+    lib.bf_batched_column_pivots.argtypes = [vp, i64, i32, i64, i32, vp, vp]
+    lib.bf_batched_column_pivots.restype = ctypes.c_int
+    lib.bf_construct_from_kernel.argtypes = [ctypes.POINTER(BFShape), i32, i32, i32, ctypes.c_uint64,
+                                             ctypes.c_double, ctypes.POINTER(BFFactorsOut), vp]
+    lib.bf_construct_from_kernel.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -122,7 +142,122 @@ def bf_last_error(handle=None):
     return msg.decode() if msg else ""
 
 
-# ---- convenience wrapper -------------------------------------------------------
+def bf_kernel_entries(kind, N, rows, nrows, cols, ncols, out, ld, stream=0):
+    return load_library().bf_kernel_entries(kind, N, rows, nrows, cols, ncols, out, ld,
+                                            ctypes.c_void_p(stream))
+
+
+def bf_batched_svd(A, batch, m, n, U, s, V, stream=0):
+    return load_library().bf_batched_svd(A, batch, m, n, U, s, V, ctypes.c_void_p(stream))
+
+
+def bf_batched_qr(A, batch, n, k, R, stream=0):
+    return load_library().bf_batched_qr(A, batch, n, k, R, ctypes.c_void_p(stream))
+
+
+def bf_batched_column_pivots(At, batch, p, n, npiv, piv, stream=0):
+    return load_library().bf_batched_column_pivots(At, batch, p, n, npiv, piv, ctypes.c_void_p(stream))
+
+
+def bf_construct_from_kernel(shape, kind, q, iters, seed, drop_rel, out, stream=0):
+    return load_library().bf_construct_from_kernel(ctypes.byref(shape), kind, q, iters, seed, drop_rel,
+                                                   ctypes.byref(out), ctypes.c_void_p(stream))
+
+
+# ---- convenience wrappers ------------------------------------------------------
+
+def _raise_on(st):
+    if st != BF_OK:
+        raise BFError(st, bf_last_error(None))
+
+
+def _cuda_c128(x, name):
+    import torch
+    if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.complex128):
+        raise TypeError(f"{name}: expected a complex128 CUDA tensor")
+    return x.contiguous()
+
+
+def kernel_entries(kernel, N, rows, cols, stream=None):
+    """K[rows][:, cols] of a built-in kernel ("fourier" or "fio"), computed on the GPU.
+
+    rows, cols: int64 CUDA tensors.  Returns a complex128 CUDA tensor."""
+    import torch
+    rows = rows.to(torch.int64).contiguous()
+    cols = cols.to(torch.int64).contiguous()
+    out = torch.empty((rows.numel(), cols.numel()), dtype=torch.complex128, device=rows.device)
+    _raise_on(bf_kernel_entries(KERNELS[kernel], int(N), rows.data_ptr(), rows.numel(), cols.data_ptr(),
+                                cols.numel(), out.data_ptr(), cols.numel(), _stream_ptr(stream)))
+    return out
+
+
+def batched_svd(A, stream=None):
+    """Thin SVD of every matrix of A [batch][m][n] (complex128, CUDA): (U, s, V), A = U diag(s) V^*."""
+    import torch
+    A = _cuda_c128(A, "A")
+    bt, m, n = A.shape
+    U = torch.empty((bt, m, n), dtype=A.dtype, device=A.device)
+    s = torch.empty((bt, n), dtype=torch.float64, device=A.device)
+    V = torch.empty((bt, n, n), dtype=A.dtype, device=A.device)
+    _raise_on(bf_batched_svd(A.data_ptr(), bt, m, n, U.data_ptr(), s.data_ptr(), V.data_ptr(),
+                             _stream_ptr(stream)))
+    return U, s, V
+
+
+def batched_qr(A, stream=None):
+    """QR of every matrix of A [batch][n][k] (complex128, CUDA): returns (Q, R); A is not modified."""
+    import torch
+    Q = _cuda_c128(A, "A").clone()
+    bt, n, k = Q.shape
+    R = torch.empty((bt, k, k), dtype=Q.dtype, device=Q.device)
+    _raise_on(bf_batched_qr(Q.data_ptr(), bt, n, k, R.data_ptr(), _stream_ptr(stream)))
+    return Q, R
+
+
+def batched_column_pivots(A, npiv, stream=None):
+    """First npiv column pivots of a column-pivoted QR of every p x n matrix of A [batch][p][n]."""
+    import torch
+    At = _cuda_c128(A, "A").transpose(1, 2).contiguous()
+    bt, n, p = At.shape
+    piv = torch.empty((bt, npiv), dtype=torch.int64, device=At.device)
+    _raise_on(bf_batched_column_pivots(At.data_ptr(), bt, p, n, npiv, piv.data_ptr(), _stream_ptr(stream)))
+    return piv
+
+
+def construct_on_device(N, radix, leaf, r, kernel="fio", q=3, iters=3, seed=0, drop_rel=1e-14,
+                        stream=None):
+    """Butterfly factorization of a built-in kernel built on the current GPU in FP64.
+
+    Randomized sampling (Alg. 2.2) on every middle-level block and the recursion of
+    Sec. 3.2, all in the library's HIP kernels.  Returns the canonical host factor
+    dict (numpy, complex128), as BFHandle takes it.  The library currently answers
+    BF_ERR_UNSUPPORTED (raised as BFError): the device driver is switched off while
+    a device-only error in it is found (include/bf_construct.h)."""
+    R, leaf, r = int(radix), int(leaf), int(r)
+    P, rem = divmod(int(N), leaf)
+    L = 0
+    while R ** L < P:
+        L += 1
+    if rem or R ** L != P:
+        raise ValueError("N / leaf must be a power of the radix")
+    h = L // 2
+    m = R ** h
+    f = {"radix": R, "leaf": leaf, "L": L, "r": r,
+         "VL": np.zeros((P, leaf, r), dtype=np.complex128),
+         "UL": np.zeros((P, leaf, r), dtype=np.complex128),
+         "S": np.zeros((m, m, r)),
+         "H": [np.zeros((R ** (l + 1), R ** (L - l - 1), r, R * r), dtype=np.complex128) for l in range(h, L)],
+         "G": [np.zeros((R ** (l + 1), R ** (L - l - 1), r, R * r), dtype=np.complex128) for l in range(h, L)]}
+    Harr = (_PD * max(1, h))(*[_ptr(x.view(np.float64)) for x in f["H"]])
+    Garr = (_PD * max(1, h))(*[_ptr(x.view(np.float64)) for x in f["G"]])
+    out = BFFactorsOut(_ptr(f["VL"].view(np.float64)), Harr, _ptr(f["S"]), Garr, _ptr(f["UL"].view(np.float64)))
+    shape = BFShape(R, leaf, L, r, int(N))
+    _raise_on(bf_construct_from_kernel(shape, KERNELS[kernel], int(q), int(iters), int(seed), float(drop_rel),
+                                       out, _stream_ptr(stream) if stream is not None else 0))
+    return f
+
+
+# ---- handle wrapper ------------------------------------------------------------
 
 def _as_f64(a):
     a = np.ascontiguousarray(a)

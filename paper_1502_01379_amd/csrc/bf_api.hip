@@ -308,6 +308,10 @@ void prof_drain(bf_plan *p) {
 }
 }  // namespace
 
+namespace bfly {
+void set_create_error(const std::string &msg) { g_create_error = msg; }
+}  // namespace bfly
+
 extern "C" {
 
 bf_status bf_create_from_factors(const bf_shape *shape, const bf_factors_host *f,

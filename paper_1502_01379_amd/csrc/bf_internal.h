@@ -158,6 +158,9 @@ hipError_t fused_run(bf_plan *p, bool adjoint, const void *g, void *u, int64_t n
                      void *buf0, void *buf1, hipStream_t s);
 void fused_free(FusedPass *fp);
 
+// Message returned by bf_last_error(NULL) on this thread (bf_api.hip)
+void set_create_error(const std::string &msg);
+
 // Profiling hooks (bf_api.hip)
 void prof_begin(bf_plan *p, const std::string &name, hipStream_t s);
 void prof_end(bf_plan *p, hipStream_t s);

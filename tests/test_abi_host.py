@@ -13,7 +13,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _declared_symbols():
-    src = open(os.path.join(ROOT, "include", "bf.h")).read()
+    inc = os.path.join(ROOT, "include")
+    src = "".join(open(os.path.join(inc, f)).read() for f in sorted(os.listdir(inc)) if f.endswith(".h"))
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     return sorted(set(re.findall(r"\b(bf_[a-z_]+)\s*\(", src)))
 
@@ -94,3 +95,41 @@ def test_null_handle_calls(lib):
     assert B.bf_backward(None, 1, 2, 3, None, 1, 1) == B.BF_ERR_INVALID_ARG
     B.bf_destroy(None)   # no-op
     assert lib.bf_set_profiling(None, 1) == B.BF_ERR_INVALID_ARG
+
+
+def test_construction_entry_points_reject_bad_arguments(lib):
+    """Argument checks of include/bf_construct.h that return before any device work."""
+    PD = ctypes.POINTER(ctypes.c_double)
+    z = np.zeros(64)
+    arr = (PD * 4)(*[z.ctypes.data_as(PD)] * 4)
+    out = B.BFFactorsOut(z.ctypes.data_as(PD), arr, z.ctypes.data_as(PD), arr, z.ctypes.data_as(PD))
+    cases = [
+        (B.BFShape(2, 16, 5, 16, 16 * 32), 1, 3, 3, B.BF_ERR_SHAPE),       # odd L
+        (B.BFShape(2, 16, 4, 16, 1000), 1, 3, 3, B.BF_ERR_SHAPE),          # N != leaf R^L
+        (B.BFShape(2, 16, 4, 16, 256), 7, 3, 3, B.BF_ERR_INVALID_ARG),     # unknown kernel
+        (B.BFShape(2, 16, 4, 16, 256), 1, 0, 3, B.BF_ERR_INVALID_ARG),     # q = 0
+        (B.BFShape(2, 1, 4, 8, 16), 1, 3, 3, B.BF_ERR_UNSUPPORTED),        # r > b = 4
+        (B.BFShape(2, 64, 4, 40, 1024), 1, 3, 3, B.BF_ERR_UNSUPPORTED),    # r > 32
+        (B.BFShape(4, 16, 2, 32, 256), 1, 3, 3, B.BF_ERR_UNSUPPORTED),     # R r > 64
+    ]
+    for shape, kind, q, iters, code in cases:
+        st = B.bf_construct_from_kernel(shape, kind, q, iters, 0, 1e-14, out)
+        assert st == code, (shape.N, kind, q, st, B.bf_last_error(None))
+        assert B.bf_last_error(None)
+    assert B.bf_batched_svd(None, 1, 4, 4, None, None, None) == B.BF_ERR_INVALID_ARG
+    assert B.bf_batched_svd(1, 1, 200, 4, None, 1, 1) == B.BF_ERR_UNSUPPORTED
+    assert B.bf_batched_svd(1, 1, 64, 65, None, 1, 1) == B.BF_ERR_UNSUPPORTED
+    assert B.bf_batched_qr(1, 1, 8, 65, None) == B.BF_ERR_UNSUPPORTED
+    assert B.bf_batched_column_pivots(1, 1, 129, 8, 2, 1) == B.BF_ERR_UNSUPPORTED
+    assert B.bf_batched_column_pivots(1, 1, 8, 8, 9, 1) == B.BF_ERR_UNSUPPORTED
+    assert B.bf_kernel_entries(5, 16, 1, 1, 1, 1, 1, 1) == B.BF_ERR_INVALID_ARG
+    assert B.bf_kernel_entries(1, 16, 1, 2, 1, 4, 1, 3) == B.BF_ERR_INVALID_ARG  # ld < ncols
+
+
+def test_device_construction_driver_is_switched_off(lib):
+    PD = ctypes.POINTER(ctypes.c_double)
+    z = np.zeros(1 << 14)
+    arr = (PD * 4)(*[z.ctypes.data_as(PD)] * 4)
+    out = B.BFFactorsOut(z.ctypes.data_as(PD), arr, z.ctypes.data_as(PD), arr, z.ctypes.data_as(PD))
+    st = B.bf_construct_from_kernel(B.BFShape(2, 4, 4, 16, 64), 1, 3, 3, 0, 1e-14, out)
+    assert st == B.BF_ERR_UNSUPPORTED and "switched off" in B.bf_last_error(None)
