@@ -124,6 +124,67 @@ __global__ void k_leaf_in_col(const typename Cx<T>::type *__restrict__ W,
   }
 }
 
+// Leaf-in with the leaf index uniform across each wavefront (npad a multiple of 64, so
+// the 64 columns of a wavefront share one leaf): the n0 x r leaf block is then read
+// with scalar loads (read-only, uniform addresses), in order, instead of once per
+// column through the vector memory path.
+template <class T, int N0, int RR>
+__global__ __launch_bounds__(256) void k_leaf_in_uni(const typename Cx<T>::type *__restrict__ W,
+                                                     const typename Cx<T>::type *__restrict__ x,
+                                                     int64_t ld, typename Cx<T>::type *__restrict__ y,
+                                                     int64_t P, int64_t nrhs, int64_t npad, int cs) {
+  using C = typename Cx<T>::type;
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= P * npad) return;
+  const int64_t n = t % npad;
+  const int64_t j = __builtin_amdgcn_readfirstlane((int)(t / npad));
+  C v[N0];
+#pragma unroll
+  for (int p = 0; p < N0; ++p) v[p] = n < nrhs ? x[(j * N0 + p) * ld + n] : C{0, 0};
+  const C *w = W + j * N0 * RR;
+  C acc[RR];
+#pragma unroll
+  for (int a = 0; a < RR; ++a) acc[a] = C{0, 0};
+#pragma unroll
+  for (int p = 0; p < N0; ++p) {
+#pragma unroll
+    for (int a = 0; a < RR; ++a) {
+      const C c = cmulc(v[p], w[p * RR + a]);
+      acc[a].x += c.x;
+      acc[a].y += c.y;
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < RR; ++a) y[act_off(j, a, n, P, RR, cs)] = acc[a];
+}
+
+// Leaf-out with the leaf index uniform across each wavefront (nrhs a multiple of 64).
+template <class T, int RR>
+__global__ __launch_bounds__(256) void k_leaf_out_uni(const typename Cx<T>::type *__restrict__ W,
+                                                      const typename Cx<T>::type *__restrict__ z,
+                                                      typename Cx<T>::type *__restrict__ u, int64_t ld,
+                                                      int64_t P, int n0, int64_t nrhs, int cs) {
+  using C = typename Cx<T>::type;
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= P * nrhs) return;
+  const int64_t n = t % nrhs;
+  const int64_t i = __builtin_amdgcn_readfirstlane((int)(t / nrhs));
+  C v[RR];
+#pragma unroll
+  for (int a = 0; a < RR; ++a) v[a] = z[act_off(i, a, n, P, RR, cs)];
+  for (int p = 0; p < n0; ++p) {
+    const C *w = W + (i * n0 + p) * RR;
+    C acc{0, 0};
+#pragma unroll
+    for (int a = 0; a < RR; ++a) {
+      const C c = cmul(w[a], v[a]);
+      acc.x += c.x;
+      acc.y += c.y;
+    }
+    u[(i * n0 + p) * ld + n] = acc;
+  }
+}
+
 template <class T, int RR>
 __global__ void k_leaf_out_col(const typename Cx<T>::type *__restrict__ W,
                                const typename Cx<T>::type *__restrict__ z,
@@ -293,6 +354,18 @@ hipError_t level_op_t(const bf_plan *p, const LevelOp &op, const void *in, int64
   const int bs = 256;
   switch (op.kind) {
     case LevelOp::kLeafIn:
+      if (npad % 64 == 0 && (p->n0 == 16 || p->n0 == 4) && (p->r == 32 || p->r == 16 || p->r == 8) &&
+          p->P * npad < (int64_t(1) << 31)) {
+        const dim3 grid(blocks_for(p->P * npad, bs));
+#define BF_LEAF_IN_UNI(N0, RR)                                                                  \
+  if (p->n0 == N0 && p->r == RR)                                                                \
+    hipLaunchKernelGGL((k_leaf_in_uni<T, N0, RR>), grid, dim3(bs), 0, s, (const C *)op.mat,     \
+                       (const C *)in, ld_in, (C *)out, p->P, nrhs, npad, cs);
+        BF_LEAF_IN_UNI(16, 32) BF_LEAF_IN_UNI(16, 16) BF_LEAF_IN_UNI(16, 8)
+        BF_LEAF_IN_UNI(4, 32) BF_LEAF_IN_UNI(4, 16) BF_LEAF_IN_UNI(4, 8)
+#undef BF_LEAF_IN_UNI
+        break;
+      }
       if (p->n0 == 16 || p->n0 == 4) {
         const dim3 grid(blocks_for(p->P * npad, bs));
         if (p->n0 == 16)
@@ -319,6 +392,20 @@ hipError_t level_op_t(const bf_plan *p, const LevelOp &op, const void *in, int64
                          op.tconj ? 1 : 0, npad, cs);
       break;
     case LevelOp::kLeafOut:
+      if (nrhs % 64 == 0 && (p->r == 32 || p->r == 16 || p->r == 8) &&
+          p->P * nrhs < (int64_t(1) << 31)) {
+        const dim3 grid(blocks_for(p->P * nrhs, bs));
+        if (p->r == 32)
+          hipLaunchKernelGGL((k_leaf_out_uni<T, 32>), grid, dim3(bs), 0, s, (const C *)op.mat,
+                             (const C *)in, (C *)out, ld_out, p->P, p->n0, nrhs, cs);
+        else if (p->r == 16)
+          hipLaunchKernelGGL((k_leaf_out_uni<T, 16>), grid, dim3(bs), 0, s, (const C *)op.mat,
+                             (const C *)in, (C *)out, ld_out, p->P, p->n0, nrhs, cs);
+        else
+          hipLaunchKernelGGL((k_leaf_out_uni<T, 8>), grid, dim3(bs), 0, s, (const C *)op.mat,
+                             (const C *)in, (C *)out, ld_out, p->P, p->n0, nrhs, cs);
+        break;
+      }
       if (p->r == 32 || p->r == 16 || p->r == 8) {
         const dim3 grid(blocks_for(p->P * nrhs, bs));
         if (p->r == 32)

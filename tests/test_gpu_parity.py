@@ -218,3 +218,25 @@ def test_hankel_sum_workload(dev, prec):
     dense = kernels.dense_apply_rows(kern, rows, g)
     e_gpu, e_ora = oracle.rel_err(u[rows], dense), oracle.rel_err(ref[rows], dense)
     assert abs(e_gpu - e_ora) <= 2 * TOL[prec] + 1e-3 * e_ora
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("radix,leaf,L,r", [(2, 16, 4, 8), (2, 16, 4, 32), (4, 16, 2, 32), (2, 4, 6, 8),
+                                            (4, 4, 4, 16), (2, 4, 4, 32)])
+@pytest.mark.parametrize("nrhs,pad", [(64, 0), (192, 0), (128, 8)])
+def test_leaf_kernels_with_wave_uniform_leaves(dev, prec, radix, leaf, L, r, nrhs, pad):
+    """Column counts that are multiples of 64 put every wavefront of the leaf kernels on
+    one leaf (leaf blocks read through the scalar path); apply and adjoint against the
+    oracle, with and without row padding."""
+    f = synthetic_factors(radix, leaf, L, r, seed=31)
+    N = leaf * radix ** L
+    g = complex_gaussian((N, nrhs), 32)
+    h = _handle(f, prec)
+    assert h.path == 0
+    tol = 1e-10 if prec == "f64" else 1e-5
+    gd = _to(np.concatenate([g, np.zeros((N, pad))], 1), dev, prec)[:, :nrhs]
+    u = h.apply(gd).cpu().numpy()
+    assert oracle.rel_err(u, oracle.bf_apply(f, g)) < tol
+    v = h.apply_adjoint(gd).cpu().numpy()
+    assert oracle.rel_err(v, oracle.bf_apply_adjoint(f, g)) < tol
+    h.close()
