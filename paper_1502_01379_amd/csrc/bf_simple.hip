@@ -128,51 +128,61 @@ __global__ void k_leaf_in_col(const typename Cx<T>::type *__restrict__ W,
 // the 64 columns of a wavefront share one leaf): the n0 x r leaf block is then read
 // with scalar loads (read-only, uniform addresses), in order, instead of once per
 // column through the vector memory path.
-template <class T, int N0, int RR>
+// The r outputs of a column are split over SPLIT wavefronts (RR / SPLIT accumulators
+// per thread), which keeps the register count low enough for several wavefronts per
+// SIMD; the column's n0 inputs are read by each of them.
+template <class T, int N0, int RR, int SPLIT>
 __global__ __launch_bounds__(256) void k_leaf_in_uni(const typename Cx<T>::type *__restrict__ W,
                                                      const typename Cx<T>::type *__restrict__ x,
                                                      int64_t ld, typename Cx<T>::type *__restrict__ y,
                                                      int64_t P, int64_t nrhs, int64_t npad, int cs) {
   using C = typename Cx<T>::type;
+  constexpr int RS = RR / SPLIT;
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (t >= P * npad) return;
+  if (t >= P * SPLIT * npad) return;
   const int64_t n = t % npad;
-  const int64_t j = __builtin_amdgcn_readfirstlane((int)(t / npad));
+  const int q = __builtin_amdgcn_readfirstlane((int)(t / npad));
+  const int64_t j = q / SPLIT;
+  const int a0 = (q % SPLIT) * RS;
   C v[N0];
 #pragma unroll
   for (int p = 0; p < N0; ++p) v[p] = n < nrhs ? x[(j * N0 + p) * ld + n] : C{0, 0};
-  const C *w = W + j * N0 * RR;
-  C acc[RR];
+  const C *w = W + j * N0 * RR + a0;
+  C acc[RS];
 #pragma unroll
-  for (int a = 0; a < RR; ++a) acc[a] = C{0, 0};
+  for (int a = 0; a < RS; ++a) acc[a] = C{0, 0};
 #pragma unroll
   for (int p = 0; p < N0; ++p) {
 #pragma unroll
-    for (int a = 0; a < RR; ++a) {
+    for (int a = 0; a < RS; ++a) {
       const C c = cmulc(v[p], w[p * RR + a]);
       acc[a].x += c.x;
       acc[a].y += c.y;
     }
   }
 #pragma unroll
-  for (int a = 0; a < RR; ++a) y[act_off(j, a, n, P, RR, cs)] = acc[a];
+  for (int a = 0; a < RS; ++a) y[act_off(j, a0 + a, n, P, RR, cs)] = acc[a];
 }
 
 // Leaf-out with the leaf index uniform across each wavefront (nrhs a multiple of 64).
-template <class T, int RR>
+// The n0 output rows of a leaf are split over SPLIT wavefronts (n0 / SPLIT rows each),
+// which shortens each wavefront and so the tail of the launch.
+template <class T, int RR, int SPLIT>
 __global__ __launch_bounds__(256) void k_leaf_out_uni(const typename Cx<T>::type *__restrict__ W,
                                                       const typename Cx<T>::type *__restrict__ z,
                                                       typename Cx<T>::type *__restrict__ u, int64_t ld,
                                                       int64_t P, int n0, int64_t nrhs, int cs) {
   using C = typename Cx<T>::type;
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (t >= P * nrhs) return;
+  if (t >= P * SPLIT * nrhs) return;
   const int64_t n = t % nrhs;
-  const int64_t i = __builtin_amdgcn_readfirstlane((int)(t / nrhs));
+  const int q = __builtin_amdgcn_readfirstlane((int)(t / nrhs));
+  const int64_t i = q / SPLIT;
+  const int rows = n0 / SPLIT, p0 = (q % SPLIT) * rows;
   C v[RR];
 #pragma unroll
   for (int a = 0; a < RR; ++a) v[a] = z[act_off(i, a, n, P, RR, cs)];
-  for (int p = 0; p < n0; ++p) {
+  for (int p = p0; p < p0 + rows; ++p) {
     const C *w = W + (i * n0 + p) * RR;
     C acc{0, 0};
 #pragma unroll
@@ -274,6 +284,26 @@ __global__ void k_middle(const T *__restrict__ S, const typename Cx<T>::type *__
   y[act_off(so, k, n, nslots, r, cs)] = C{s * v.x, s * v.y};
 }
 
+// As k_middle for FP32 and even r, one thread per (slot, row pair, column): rows 2kp and
+// 2kp + 1 of a column are adjacent in the activation layout (16-byte aligned), so each
+// thread moves them with one 16-byte load and store.
+__global__ void k_middle_pairs(const float *__restrict__ S, const float4 *__restrict__ x,
+                               float4 *__restrict__ y, int64_t m, int r, int transpose, int64_t npad,
+                               int cs) {
+  const int64_t nslots = m * m;
+  const int rp = r >> 1;
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= nslots * rp * npad) return;
+  const int64_t n = t % npad;
+  const int kp = (int)((t / npad) % rp);
+  const int64_t so = t / (npad * rp);
+  const int64_t a = so / m, b = so - a * m;
+  const float *sp = S + (transpose ? b * m + a : so) * r + 2 * kp;
+  const float s0 = sp[0], s1 = sp[1];
+  const float4 v = x[act_off(b * m + a, 2 * kp, n, nslots, r, cs) >> 1];
+  y[act_off(so, 2 * kp, n, nslots, r, cs) >> 1] = float4{s0 * v.x, s0 * v.y, s1 * v.z, s1 * v.w};
+}
+
 // grad[R hi + cx][lo][rx][cy r + ry] = sum_n X[strided(b,cx)][rx][n] conj(Y[contig(b,cy)][ry][n])
 template <class T>
 __global__ void k_level_grad(const typename Cx<T>::type *__restrict__ X,
@@ -355,12 +385,14 @@ hipError_t level_op_t(const bf_plan *p, const LevelOp &op, const void *in, int64
   switch (op.kind) {
     case LevelOp::kLeafIn:
       if (npad % 64 == 0 && (p->n0 == 16 || p->n0 == 4) && (p->r == 32 || p->r == 16 || p->r == 8) &&
-          p->P * npad < (int64_t(1) << 31)) {
-        const dim3 grid(blocks_for(p->P * npad, bs));
+          p->P * 2 * npad < (int64_t(1) << 31)) {
 #define BF_LEAF_IN_UNI(N0, RR)                                                                  \
-  if (p->n0 == N0 && p->r == RR)                                                                \
-    hipLaunchKernelGGL((k_leaf_in_uni<T, N0, RR>), grid, dim3(bs), 0, s, (const C *)op.mat,     \
-                       (const C *)in, ld_in, (C *)out, p->P, nrhs, npad, cs);
+  if (p->n0 == N0 && p->r == RR) {                                                              \
+    constexpr int SP = RR == 32 ? 2 : 1;                                                        \
+    hipLaunchKernelGGL((k_leaf_in_uni<T, N0, RR, SP>), dim3(blocks_for(p->P * SP * npad, bs)),  \
+                       dim3(bs), 0, s, (const C *)op.mat, (const C *)in, ld_in, (C *)out, p->P, \
+                       nrhs, npad, cs);                                                         \
+  }
         BF_LEAF_IN_UNI(16, 32) BF_LEAF_IN_UNI(16, 16) BF_LEAF_IN_UNI(16, 8)
         BF_LEAF_IN_UNI(4, 32) BF_LEAF_IN_UNI(4, 16) BF_LEAF_IN_UNI(4, 8)
 #undef BF_LEAF_IN_UNI
@@ -387,23 +419,34 @@ hipError_t level_op_t(const bf_plan *p, const LevelOp &op, const void *in, int64
                          p->P, npad, cs);
       break;
     case LevelOp::kMiddle:
+      if constexpr (sizeof(T) == 4) {
+        if (p->r % 2 == 0) {
+          hipLaunchKernelGGL(k_middle_pairs, dim3(blocks_for(p->m * p->m * (p->r / 2) * npad, bs)),
+                             dim3(bs), 0, s, (const float *)op.mat, (const float4 *)in,
+                             (float4 *)out, p->m, p->r, op.tconj ? 1 : 0, npad, cs);
+          break;
+        }
+      }
       hipLaunchKernelGGL(k_middle<T>, dim3(blocks_for(p->m * p->m * p->r * npad, bs)), dim3(bs),
                          0, s, (const T *)op.mat, (const C *)in, (C *)out, p->m, p->r,
                          op.tconj ? 1 : 0, npad, cs);
       break;
     case LevelOp::kLeafOut:
       if (nrhs % 64 == 0 && (p->r == 32 || p->r == 16 || p->r == 8) &&
-          p->P * nrhs < (int64_t(1) << 31)) {
-        const dim3 grid(blocks_for(p->P * nrhs, bs));
-        if (p->r == 32)
-          hipLaunchKernelGGL((k_leaf_out_uni<T, 32>), grid, dim3(bs), 0, s, (const C *)op.mat,
-                             (const C *)in, (C *)out, ld_out, p->P, p->n0, nrhs, cs);
-        else if (p->r == 16)
-          hipLaunchKernelGGL((k_leaf_out_uni<T, 16>), grid, dim3(bs), 0, s, (const C *)op.mat,
-                             (const C *)in, (C *)out, ld_out, p->P, p->n0, nrhs, cs);
-        else
-          hipLaunchKernelGGL((k_leaf_out_uni<T, 8>), grid, dim3(bs), 0, s, (const C *)op.mat,
-                             (const C *)in, (C *)out, ld_out, p->P, p->n0, nrhs, cs);
+          p->P * 2 * nrhs < (int64_t(1) << 31)) {
+        const bool two = p->n0 % 2 == 0;
+        const dim3 grid(blocks_for(p->P * (two ? 2 : 1) * nrhs, bs));
+#define BF_LEAF_OUT_UNI(RR)                                                                     \
+  if (p->r == RR) {                                                                             \
+    if (two)                                                                                    \
+      hipLaunchKernelGGL((k_leaf_out_uni<T, RR, 2>), grid, dim3(bs), 0, s, (const C *)op.mat,   \
+                         (const C *)in, (C *)out, ld_out, p->P, p->n0, nrhs, cs);               \
+    else                                                                                        \
+      hipLaunchKernelGGL((k_leaf_out_uni<T, RR, 1>), grid, dim3(bs), 0, s, (const C *)op.mat,   \
+                         (const C *)in, (C *)out, ld_out, p->P, p->n0, nrhs, cs);               \
+  }
+        BF_LEAF_OUT_UNI(32) BF_LEAF_OUT_UNI(16) BF_LEAF_OUT_UNI(8)
+#undef BF_LEAF_OUT_UNI
         break;
       }
       if (p->r == 32 || p->r == 16 || p->r == 8) {

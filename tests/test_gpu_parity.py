@@ -222,7 +222,7 @@ def test_hankel_sum_workload(dev, prec):
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("radix,leaf,L,r", [(2, 16, 4, 8), (2, 16, 4, 32), (4, 16, 2, 32), (2, 4, 6, 8),
-                                            (4, 4, 4, 16), (2, 4, 4, 32)])
+                                            (4, 4, 4, 16), (2, 4, 4, 32), (2, 3, 4, 8)])
 @pytest.mark.parametrize("nrhs,pad", [(64, 0), (192, 0), (128, 8)])
 def test_leaf_kernels_with_wave_uniform_leaves(dev, prec, radix, leaf, L, r, nrhs, pad):
     """Column counts that are multiples of 64 put every wavefront of the leaf kernels on
