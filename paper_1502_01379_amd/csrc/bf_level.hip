@@ -16,6 +16,8 @@
 // ahead of the one being contracted.
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
+
 #include "bf_internal.h"
 
 namespace bfly {
@@ -138,6 +140,132 @@ __global__ __launch_bounds__(BR * 2) void k_level_mfma(const f32x4 *__restrict__
   }
 }
 
+// As k_level_mfma, with the K range of the real block split over two wavefronts per
+// row group (2 BR / 32 wavefronts): wavefront (w, kh) keeps steps kh BR/2 .. kh BR/2 +
+// BR/2 - 1 of rows 32 w .. 32 w + 31, so it holds half the block rows and the register
+// count allows two workgroups per CU (one workgroup's block load overlaps the other's
+// products).  After each chunk the K-high wavefronts hand their partial sums to the
+// K-low ones through the chunk buffer just consumed, which then store the outputs.
+// Workgroup barrier without a memory fence (which would also wait for global stores and
+// copies in flight); the empty asm statements keep the compiler from moving LDS
+// accesses across it, since the barrier instruction itself does not order memory for
+// the compiler.
+__device__ __forceinline__ void wg_barrier() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
+template <int BR, int R>
+__global__ __launch_bounds__(BR * 4) __attribute__((amdgpu_waves_per_eu(4))) void k_level_mfma_ks(
+    const f32x4 *__restrict__ Ap, const f32x4 *__restrict__ x, f32x4 *__restrict__ y, int64_t blo,
+    int64_t nslots, int64_t nchunks, int strided_in) {
+  constexpr int r = BR / R;
+  constexpr int W = BR / 32;
+  constexpr int HS = BR / 2;                 // steps per K half
+  constexpr int kChunkBytes = BR * 32 * 8;   // R slots x r rows x 32 columns, complex64
+  static_assert(W * 64 * 32 * 4 <= kChunkBytes, "partial sums must fit in one chunk buffer");
+  __shared__ __attribute__((aligned(16))) char xs[2][kChunkBytes];
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int w = wv % W, kh = wv / W;
+  const int64_t b = blockIdx.x;
+  const int64_t hi = b / blo, lo = b - hi * blo;
+  constexpr int half = r / 2;
+  auto slot = [&](int c, bool strided) {
+    return strided ? hi * R * blo + c * blo + lo : hi * R * blo + R * lo + c;
+  };
+  static_assert(r % 32 == 0, "a 32-row group of outputs must lie in one slot");
+  // input slot c of this butterfly is s_in0 + c * dc_in (both uniform)
+  const int64_t s_in0 = slot(0, strided_in != 0), dc_in = strided_in ? blo : 1;
+  const int64_t s_out0 = slot(0, strided_in == 0), dc_out = strided_in ? 1 : blo;
+  auto issue = [&](int64_t ch) {
+    char *dst = xs[ch & 1];
+    const f32x4 *xb = x + (ch * nslots + s_in0) * (half * 32);
+#pragma unroll
+    for (int k = 0; k < (BR * 16) / (BR * 4); ++k) {
+      constexpr int kPerSlot = (half * 32) / (BR * 4);  // pieces of one slot per thread
+      const int c = k / kPerSlot, part = k % kPerSlot;
+      const f32x4 *src = xb + c * dc_in * (half * 32) + part * (BR * 4) + threadIdx.x;
+      __builtin_amdgcn_global_load_lds(src,
+                                       (__attribute__((address_space(3))) void *)(dst + (k * BR * 4 + threadIdx.x) * 16),
+                                       16, 0, 0);
+    }
+  };
+  issue(0);
+  float a[HS];
+  {
+    const f32x4 *src = Ap + (b * W + w) * (BR / 4) * 64 + kh * (HS / 4) * 64 + lane;
+#pragma unroll
+    for (int s4 = 0; s4 < HS / 4; ++s4) {
+      const f32x4 v = src[s4 * 64];
+      a[4 * s4] = v.x;
+      a[4 * s4 + 1] = v.y;
+      a[4 * s4 + 2] = v.z;
+      a[4 * s4 + 3] = v.w;
+    }
+  }
+  const int j = lane & 31, kk = lane >> 5;
+  for (int64_t ch = 0; ch < nchunks; ++ch) {
+    // this chunk's copies have landed: the K-low wavefronts may still have their eight
+    // output stores of the previous chunk in flight, issued after the copies; the
+    // K-high wavefronts store nothing
+    if (ch == 0 || kh == 1)
+      __builtin_amdgcn_s_waitcnt(0);
+    else
+      __builtin_amdgcn_s_waitcnt(0xf78);  // vmcnt(8)
+    wg_barrier();
+    if (ch + 1 < nchunks) issue(ch + 1);
+    const float *xc = reinterpret_cast<const float *>(xs[ch & 1]);
+    floatx16 dre = {}, dim = {};
+#pragma unroll
+    for (int s2 = 0; s2 < HS; ++s2) {
+      // step s = kh HS + s2: the K-low half reads [Re x; Im x] rows, the K-high half
+      // [Im x; -Re x], both at row pair s2 of the buffer
+      const float *e = xc + (s2 * 32 + j) * 4 + kk * 2;
+      const float xr = e[0], xi = e[1];
+      const float bre = kh == 0 ? xr : xi;
+      const float bim = kh == 0 ? xi : -xr;
+      dre = __builtin_amdgcn_mfma_f32_32x32x2f32(a[s2], bre, dre, 0, 0, 0);
+      dim = __builtin_amdgcn_mfma_f32_32x32x2f32(a[s2], bim, dim, 0, 0, 0);
+      // keep the scheduler from hoisting every step's buffer reads (registers)
+      if (s2 % 8 == 7) __builtin_amdgcn_sched_barrier(0);
+    }
+    // every wavefront is done reading this buffer; the K-high ones put their partial
+    // sums there, the K-low ones add them
+    wg_barrier();
+    float *red = reinterpret_cast<float *>(xs[ch & 1]) + (w * 64 + lane) * 32;
+    if (kh == 1) {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        red[i] = dre[i];
+        red[16 + i] = dim[i];
+      }
+    }
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
+    wg_barrier();
+    if (kh == 0) {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        dre[i] += red[i];
+        dim[i] += red[16 + i];
+      }
+      // lane (j, eta) holds rows 32 w + 8 q + 4 eta + v of column j: output slot co =
+      // 32 w / r, rows row0 + 8 q + 4 eta + v with row0 = 32 w - co r
+      const int co = (32 * w) / r, row0 = 32 * w - co * r;
+      f32x4 *yb = y + ((ch * nslots + s_out0 + co * dc_out) * half + row0 / 2 + 2 * kk) * 32 + j;
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int v = 0; v < 4; v += 2) {
+          const f32x4 val = {dre[4 * q + v], dim[4 * q + v], dre[4 * q + v + 1], dim[4 * q + v + 1]};
+          yb[(4 * q + v / 2) * 32] = val;
+        }
+    }
+  }
+}
+
 }  // namespace
 
 bool level_mfma_supported(int R, int r) {
@@ -168,9 +296,15 @@ hipError_t launch_level_mfma(const bf_plan *p, const LevelOp &op, const void *in
   else if (BR == 64)
     hipLaunchKernelGGL(k_level_mfma<64>, dim3((unsigned)op.nb), dim3(128), 0, s, A, x, y, op.blo, p->P,
                        nchunks, p->R, p->r, strided);
-  else
+  else if (std::getenv("BF_LEVEL_NO_KSPLIT"))
     hipLaunchKernelGGL(k_level_mfma<128>, dim3((unsigned)op.nb), dim3(256), 0, s, A, x, y, op.blo, p->P,
                        nchunks, p->R, p->r, strided);
+  else if (p->R == 4)
+    hipLaunchKernelGGL((k_level_mfma_ks<128, 4>), dim3((unsigned)op.nb), dim3(512), 0, s, A, x, y, op.blo,
+                       p->P, nchunks, strided);
+  else
+    hipLaunchKernelGGL((k_level_mfma_ks<128, 2>), dim3((unsigned)op.nb), dim3(512), 0, s, A, x, y, op.blo,
+                       p->P, nchunks, strided);
   return hipGetLastError();
 }
 
