@@ -250,6 +250,8 @@ __global__ __launch_bounds__(BR * 4) __attribute__((amdgpu_waves_per_eu(4))) voi
       for (int i = 0; i < 16; ++i) {
         dre[i] += red[i];
         dim[i] += red[16 + i];
+        // a few partial sums in flight at a time (registers)
+        if (i % 4 == 3) __builtin_amdgcn_sched_barrier(0);
       }
       // lane (j, eta) holds rows 32 w + 8 q + 4 eta + v of column j: output slot co =
       // 32 w / r, rows row0 + 8 q + 4 eta + v with row0 = 32 w - co r
