@@ -52,11 +52,6 @@ def form_usv(U0, s, V0h, drop_rel=1e-14):
     return U, S, Vs.conj().T                            # V with V^* = S0 V0^*
 
 
-def form_u_sigma(U0, s, V0h):
-    """Third equivalent form (Sec. 2): U = U0 S0, V^* = V0^*."""
-    return U0 * s[None, :], V0h
-
-
 def _pivoted_qr(A):
     Q, Rm, piv = sla.qr(A, mode="economic", pivoting=True)
     return Q, Rm, piv

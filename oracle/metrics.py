@@ -16,12 +16,3 @@ def rel_err(u_a, u_d):
     den = np.sum(np.abs(u_d) ** 2)
     return float(np.sqrt(num / den)) if den > 0 else float(np.sqrt(num))
 
-
-def rel_err_per_column(u_a, u_d):
-    u_a = np.asarray(u_a, dtype=np.complex128)
-    u_d = np.asarray(u_d, dtype=np.complex128)
-    if u_a.ndim == 1:
-        return np.array([rel_err(u_a, u_d)])
-    num = np.sum(np.abs(u_a - u_d) ** 2, axis=0)
-    den = np.sum(np.abs(u_d) ** 2, axis=0)
-    return np.sqrt(num / den)

@@ -130,3 +130,19 @@ def test_dense_apply_rows():
     u = kernels.dense_apply_rows(kern, rows, g, col_chunk=100)
     ref = kern.entries(rows, np.arange(N)) @ g
     assert np.abs(u - ref).max() < 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("N", [64, 1024])
+def test_hankel_points_from_the_wronskian(N):
+    # Example 2 places row i (0-based) at x_i = N + (2 pi / 3) i.  For Hankel
+    # functions of the first kind, J_{v+1} Y_v - J_v Y_{v+1} = 2 / (pi x), so
+    # Im(H_{v+1}(x) conj(H_v(x))) = -2 / (pi x): two neighbouring columns of a
+    # row give back that row's point, whatever the entries' formula says.
+    kern = kernels.HankelSum(N)
+    rows = np.array([0, 1, 2, 7, N // 2 + 3, N - 1])
+    for v in (0, 5, N // 3, N - 2):
+        K = kern.entries(rows, np.array([v, v + 1]))
+        w = np.imag(K[:, 1] * np.conj(K[:, 0]))
+        x = -2.0 / (np.pi * w)
+        expect = N + (2.0 * np.pi / 3.0) * rows
+        assert np.abs(x / expect - 1).max() < 1e-10
