@@ -77,9 +77,11 @@ typedef enum {
   BF_PREC_F64 = 0,        /* complex128 vectors, FP64 arithmetic                             */
   BF_PREC_F32 = 1,        /* complex64 vectors, FP32 arithmetic                              */
   BF_PREC_SPLIT_BF16 = 2, /* complex64 vectors; block products as three BF16 MFMA products   */
-                          /* (hi*hi + hi*lo + lo*hi) with FP32 accumulation, per-block and   */
-                          /* per-column power-of-two scaling                                 */
-  BF_PREC_SPLIT_F16 = 3   /* as SPLIT_BF16 with FP16 halves                                  */
+                          /* (hi*hi + hi*lo + lo*hi) with FP32 accumulation.  No scaling:    */
+                          /* BF16 has the exponent range of FP32, and a power-of-two scale   */
+                          /* would not change a single rounding                              */
+  BF_PREC_SPLIT_F16 = 3   /* as SPLIT_BF16 with FP16 halves; every block and every column    */
+                          /* of a block product is scaled by a power of two into FP16 range  */
 } bf_precision;
 
 typedef struct {
@@ -114,21 +116,53 @@ typedef struct {
 /* Validate `shape` and `factors`, pack the factors for `precision` and copy
  * them to the current HIP device.  Synchronizes `stream` before returning; the
  * caller may free its host arrays afterwards.  On success *out is a new handle.
- * Errors: BF_ERR_INVALID_ARG, BF_ERR_SHAPE, BF_ERR_UNSUPPORTED, BF_ERR_NONFINITE,
- * BF_ERR_ALLOC, BF_ERR_HIP. */
+ * The factors are those of the factor product of Sec. 1.2 (eq. (1)) as Sec. 3.1
+ * and 3.2 build them.  Errors: BF_ERR_INVALID_ARG, BF_ERR_SHAPE,
+ * BF_ERR_UNSUPPORTED, BF_ERR_NONFINITE, BF_ERR_ALLOC, BF_ERR_HIP. */
 bf_status bf_create_from_factors(const bf_shape *shape, const bf_factors_host *factors,
                                  bf_precision precision, hipStream_t stream, bf_handle *out);
+
+/* Kernel-path choices of a handle.  A zero-filled struct (or NULL) gives the
+ * defaults that bf_create_from_factors uses; the other values select variants
+ * of the same arithmetic, for comparisons and tests.  Results of every variant
+ * agree to within the precision's tolerance. */
+typedef struct {
+  int32_t path;         /* 0: fused MFMA passes where the shape allows them (radix 2, */
+                        /*    leaf 16, r 16, not FP64), else per-level kernels;        */
+                        /* 1: per-level kernels (FP64 and FP32 only)                   */
+  int32_t fused_cols;   /* fused passes: columns per wavefront, 0 (= 16) or 32          */
+  int32_t fused_kmax;   /* fused passes: deepest pass in levels, 0 = 4 (16 columns) or  */
+                        /* 3 (32 columns); 1 .. that maximum                            */
+  int32_t fused_split;  /* fused passes: passes of at least this many levels share a   */
+                        /* tile between two wavefronts; 0 = 4, -1 = never              */
+  int32_t level_mfma;   /* per-level FP32 butterflies with R r in {32, 64, 128}:        */
+                        /* 0 = on the matrix cores, -1 = one thread per output value    */
+  int32_t level_ksplit; /* R r = 128 on the matrix cores: 0 = K range split over two    */
+                        /* wavefronts, -1 = one wavefront per row group                 */
+} bf_plan_options;
+
+/* bf_create_from_factors with explicit kernel-path choices (opts may be NULL).
+ * Errors as bf_create_from_factors; BF_ERR_INVALID_ARG for a value outside the
+ * ranges above. */
+bf_status bf_create_from_factors_ex(const bf_shape *shape, const bf_factors_host *factors,
+                                    bf_precision precision, const bf_plan_options *opts,
+                                    hipStream_t stream, bf_handle *out);
 
 /* u = K_BF g for nrhs columns (Sec. 1.2: a sequence of O(log N) sparse
  * products, applied right to left).  g, u: device [N][ld]. */
 bf_status bf_apply(bf_handle h, const void *g, void *u, int64_t nrhs, int64_t ld,
                    hipStream_t stream);
 
-/* v = K_BF^* w: the factors in reverse order, each conjugate-transposed. */
+/* v = K_BF^* w: the conjugate transpose of the factor product of Sec. 1.2
+ * (eq. (1)), i.e. the factors in reverse order, each conjugate-transposed:
+ * V^L H^{L-1} ... H^h (M^h)^T (G^h)^* ... (G^{L-1})^* (U^L)^*.  Arguments,
+ * layouts and errors as bf_apply. */
 bf_status bf_apply_adjoint(bf_handle h, const void *w, void *v, int64_t nrhs, int64_t ld,
                            hipStream_t stream);
 
-/* Gradients of a real loss through u = K_BF g.  grad_u = dL/dRe(u) + i dL/dIm(u)
+/* Gradients of a real loss through u = K_BF g.  The paper defines no
+ * gradients; this is the chain rule through the factor product of Sec. 1.2,
+ * with the complex convention grad = dL/dRe + i dL/dIm.  grad_u = dL/dRe(u) + i dL/dIm(u)
  * ([N][ld], device).  Writes grad_g = K_BF^* grad_u (if non-NULL) and, for every
  * non-NULL pointer in `grads`, the gradient of that factor:
  *   forward-applied blocks B (G, U^L):      grad_B = sum_n d_out x_in^*

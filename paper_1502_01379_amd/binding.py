@@ -22,7 +22,7 @@ PRECISIONS = {"f64": 0, "f32": 1, "bf16x3": 2, "f16x3": 3}
 BF_BWD_RECOMPUTE = 0
 BF_BWD_STORE_ALL = 1
 
-EXPORTED = ["bf_create_from_factors", "bf_apply", "bf_apply_adjoint", "bf_backward", "bf_destroy",
+EXPORTED = ["bf_create_from_factors", "bf_create_from_factors_ex", "bf_apply", "bf_apply_adjoint", "bf_backward", "bf_destroy",
             "bf_last_error", "bf_query", "bf_set_profiling", "bf_kernel_times",
             # include/bf_construct.h
             "bf_kernel_entries", "bf_batched_svd", "bf_batched_qr", "bf_batched_column_pivots",
@@ -36,6 +36,12 @@ class BFShape(ctypes.Structure):
 
 
 _PD = ctypes.POINTER(ctypes.c_double)
+
+
+class BFPlanOptions(ctypes.Structure):
+    _fields_ = [("path", ctypes.c_int32), ("fused_cols", ctypes.c_int32), ("fused_kmax", ctypes.c_int32),
+                ("fused_split", ctypes.c_int32), ("level_mfma", ctypes.c_int32),
+                ("level_ksplit", ctypes.c_int32)]
 
 
 class BFFactorsHost(ctypes.Structure):
@@ -76,6 +82,9 @@ def load_library(path=LIB_PATH):
     lib.bf_create_from_factors.argtypes = [ctypes.POINTER(BFShape), ctypes.POINTER(BFFactorsHost),
                                            ctypes.c_int, vp, ctypes.POINTER(vp)]
     lib.bf_create_from_factors.restype = ctypes.c_int
+    lib.bf_create_from_factors_ex.argtypes = [ctypes.POINTER(BFShape), ctypes.POINTER(BFFactorsHost),
+                                              ctypes.c_int, ctypes.POINTER(BFPlanOptions), vp, ctypes.POINTER(vp)]
+    lib.bf_create_from_factors_ex.restype = ctypes.c_int
     for name in ("bf_apply", "bf_apply_adjoint"):
         fn = getattr(lib, name)
         fn.argtypes = [vp, vp, vp, i64, i64, vp]
@@ -116,6 +125,16 @@ def bf_create_from_factors(shape, factors, precision, stream=0):
     h = ctypes.c_void_p()
     st = lib.bf_create_from_factors(ctypes.byref(shape), ctypes.byref(factors), int(precision),
                                     ctypes.c_void_p(stream), ctypes.byref(h))
+    return st, h.value
+
+
+def bf_create_from_factors_ex(shape, factors, precision, options=None, stream=0):
+    """Returns (status, handle); options is a BFPlanOptions or None (defaults)."""
+    lib = load_library()
+    h = ctypes.c_void_p()
+    st = lib.bf_create_from_factors_ex(ctypes.byref(shape), ctypes.byref(factors), int(precision),
+                                       ctypes.byref(options) if options is not None else None,
+                                       ctypes.c_void_p(stream), ctypes.byref(h))
     return st, h.value
 
 
@@ -281,7 +300,8 @@ def _stream_ptr(stream):
 class BFHandle:
     """A factorization resident on the current GPU (owns a bf_handle)."""
 
-    def __init__(self, factors, precision="f32", stream=None):
+    def __init__(self, factors, precision="f32", stream=None, options=None):
+        """options: dict of bf_plan_options fields (kernel-path variants), or None."""
         self.lib = load_library()
         f = factors
         self.radix, self.leaf, self.L, self.r = int(f["radix"]), int(f["leaf"]), int(f["L"]), int(f["r"])
@@ -296,8 +316,13 @@ class BFHandle:
         Harr = (_PD * max(1, len(Hs)))(*[_ptr(x) for x in Hs])
         Garr = (_PD * max(1, len(Gs)))(*[_ptr(x) for x in Gs])
         fh = BFFactorsHost(_ptr(keep[0]), Harr, _ptr(keep[2]), Garr, _ptr(keep[1]))
-        st, h = bf_create_from_factors(shape, fh, self.prec_code,
-                                       _stream_ptr(stream) if stream is not None else 0)
+        opts = None
+        if options:
+            opts = BFPlanOptions()
+            for k, v in options.items():
+                setattr(opts, k, int(v))
+        st, h = bf_create_from_factors_ex(shape, fh, self.prec_code, opts,
+                                          _stream_ptr(stream) if stream is not None else 0)
         if st != BF_OK:
             raise BFError(st, bf_last_error(None))
         self.handle = h

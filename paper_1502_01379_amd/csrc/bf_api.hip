@@ -316,8 +316,22 @@ extern "C" {
 
 bf_status bf_create_from_factors(const bf_shape *shape, const bf_factors_host *f,
                                  bf_precision prec, hipStream_t stream, bf_handle *out) {
+  return bf_create_from_factors_ex(shape, f, prec, nullptr, stream, out);
+}
+
+bf_status bf_create_from_factors_ex(const bf_shape *shape, const bf_factors_host *f,
+                                    bf_precision prec, const bf_plan_options *opts,
+                                    hipStream_t stream, bf_handle *out) {
   g_create_error.clear();
   if (!out) return fail(nullptr, BF_ERR_INVALID_ARG, "out is NULL");
+  bf_plan_options opt{};
+  if (opts) {
+    opt = *opts;
+    if (opt.path < 0 || opt.path > 1 || (opt.fused_cols != 0 && opt.fused_cols != 16 && opt.fused_cols != 32) ||
+        opt.fused_kmax < 0 || opt.fused_kmax > (opt.fused_cols == 32 ? 3 : 4) || opt.fused_split < -1 ||
+        opt.level_mfma < -1 || opt.level_mfma > 0 || opt.level_ksplit < -1 || opt.level_ksplit > 0)
+      return fail(nullptr, BF_ERR_INVALID_ARG, "plan option out of range");
+  }
   *out = nullptr;
   bf_status st = check_shape(shape, nullptr);
   if (st != BF_OK) return st;
@@ -333,6 +347,7 @@ bf_status bf_create_from_factors(const bf_shape *shape, const bf_factors_host *f
   if (!p) return fail(nullptr, BF_ERR_ALLOC, "host allocation failed");
   p->shape = *shape;
   p->prec = prec;
+  p->opt = opt;
   p->R = shape->radix;
   p->n0 = shape->leaf;
   p->L = shape->L;
@@ -342,7 +357,7 @@ bf_status bf_create_from_factors(const bf_shape *shape, const bf_factors_host *f
   p->m = ipow(p->R, h);
   p->N = shape->N;
 
-  const bool fused = bfly::fused_supported(*shape, prec);
+  const bool fused = bfly::fused_supported(*shape, prec, opt);
   if (!fused && (prec == BF_PREC_SPLIT_BF16 || prec == BF_PREC_SPLIT_F16)) {
     delete p;
     return fail(nullptr, BF_ERR_UNSUPPORTED,
@@ -366,8 +381,7 @@ bf_status bf_create_from_factors(const bf_shape *shape, const bf_factors_host *f
     if (fused) {
       p->path = 1;
       st = bfly::fused_build(p, f);
-    } else if (prec == BF_PREC_F32 && bfly::level_mfma_supported(p->R, p->r) &&
-               !std::getenv("BF_DISABLE_LEVEL_MFMA")) {
+    } else if (prec == BF_PREC_F32 && bfly::level_mfma_supported(p->R, p->r) && opt.level_mfma == 0) {
       // butterfly levels on the matrix cores: blocks packed on the device
       for (auto *ops : {&p->fwd_ops, &p->adj_ops})
         for (LevelOp &op : *ops) {

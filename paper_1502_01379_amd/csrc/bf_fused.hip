@@ -405,25 +405,22 @@ hipError_t launch_pass(const bf_plan *p, const FusedPass *fp, const void *in, vo
 
 }  // namespace
 
-bool fused_supported(const bf_shape &sh, bf_precision prec) {
-  if (std::getenv("BF_DISABLE_FUSED")) return false;
+bool fused_supported(const bf_shape &sh, bf_precision prec, const bf_plan_options &opt) {
+  if (opt.path == 1) return false;
   return prec != BF_PREC_F64 && sh.radix == 2 && sh.leaf == kRank && sh.r == kRank && sh.L >= 2;
 }
 
 bf_status fused_build(bf_plan *p, const bf_factors_host *f) {
   HostFactors F{f, p->L, p->h};
-  // wavefront geometry (columns per wavefront) and deepest pass; environment
-  // overrides exist for measurements
-  int cols = kDefaultCols;
-  if (const char *e = std::getenv("BF_FUSED_COLS")) cols = std::atoi(e) == 32 ? 32 : 16;
+  // wavefront geometry (columns per wavefront) and deepest pass (the handle's
+  // options can select other variants, for comparisons)
+  const int cols = p->opt.fused_cols == 32 ? 32 : kDefaultCols;
   const int kcap = cols == 32 ? 3 : 4;
   // four-level passes (four passes per apply at L = 16) for every precision
-  int kmax = kcap;
-  if (const char *e = std::getenv("BF_FUSED_KMAX")) kmax = std::max(1, std::min(kcap, std::atoi(e)));
+  const int kmax = p->opt.fused_kmax > 0 ? std::min(kcap, p->opt.fused_kmax) : kcap;
   // passes of at least split_min levels (16-column geometry) share each tile
   // between a pair of wavefronts
-  int split_min = 4;
-  if (const char *e = std::getenv("BF_FUSED_SPLIT")) split_min = std::atoi(e) <= 0 ? 99 : std::atoi(e);
+  const int split_min = p->opt.fused_split < 0 ? 99 : p->opt.fused_split > 0 ? p->opt.fused_split : 4;
   p->cs = cols == 32 ? 5 : 4;
   const int prec = p->prec == BF_PREC_F32 ? kF32 : p->prec == BF_PREC_SPLIT_BF16 ? kBF16 : kF16;
 

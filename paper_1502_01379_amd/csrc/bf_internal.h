@@ -70,6 +70,7 @@ struct ProfRec {
 struct bf_plan {
   bf_shape shape{};
   bf_precision prec = BF_PREC_F32;
+  bf_plan_options opt{};  // kernel-path choices (all zero: defaults)
   int path = 0;  // 0 = per-level kernels, 1 = fused MFMA passes
   int cs = 5;    // log2 of the activation chunk (columns per wavefront of the fused path)
   int R = 2, n0 = 0, L = 0, r = 0, h = 0;
@@ -137,7 +138,7 @@ hipError_t launch_grad_leaf_mfma(const bf_plan *p, const void *user, int64_t ld,
                                  void *grad, int64_t nrhs, hipStream_t s);
 
 // Fused path (bf_fused.hip)
-bool fused_supported(const bf_shape &sh, bf_precision prec);
+bool fused_supported(const bf_shape &sh, bf_precision prec, const bf_plan_options &opt);
 // FP32 passes of the backward pass (blocks packed on the device from the
 // canonical factors)
 bf_status fused_build_backward(bf_plan *p, hipStream_t s);

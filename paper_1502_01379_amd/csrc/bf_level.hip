@@ -298,7 +298,7 @@ hipError_t launch_level_mfma(const bf_plan *p, const LevelOp &op, const void *in
   else if (BR == 64)
     hipLaunchKernelGGL(k_level_mfma<64>, dim3((unsigned)op.nb), dim3(128), 0, s, A, x, y, op.blo, p->P,
                        nchunks, p->R, p->r, strided);
-  else if (std::getenv("BF_LEVEL_NO_KSPLIT"))
+  else if (p->opt.level_ksplit < 0)
     hipLaunchKernelGGL(k_level_mfma<128>, dim3((unsigned)op.nb), dim3(256), 0, s, A, x, y, op.blo, p->P,
                        nchunks, p->R, p->r, strided);
   else if (p->R == 4)

@@ -89,6 +89,25 @@ def test_split_precision_needs_fused_shape(lib):
     assert st == B.BF_ERR_UNSUPPORTED and not h
 
 
+@pytest.mark.parametrize("field,value", [("path", 2), ("path", -1), ("fused_cols", 8), ("fused_kmax", 5),
+                                         ("fused_split", -2), ("level_mfma", 1), ("level_ksplit", 3)])
+def test_create_ex_rejects_bad_options(lib, field, value):
+    fh, keep = _factors((2, 16, 2, 16))
+    opts = B.BFPlanOptions()
+    setattr(opts, field, value)
+    st, h = B.bf_create_from_factors_ex(B.BFShape(2, 16, 2, 16, 64), fh, 1, opts)
+    assert st == B.BF_ERR_INVALID_ARG and not h
+    assert "option" in B.bf_last_error(None)
+
+
+def test_split_precision_rejects_the_per_level_path(lib):
+    fh, keep = _factors((2, 16, 2, 16))
+    opts = B.BFPlanOptions()
+    opts.path = 1
+    st, h = B.bf_create_from_factors_ex(B.BFShape(2, 16, 2, 16, 64), fh, 2, opts)
+    assert st == B.BF_ERR_UNSUPPORTED and not h
+
+
 def test_null_handle_calls(lib):
     assert B.bf_apply(None, 1, 2, 1, 1) == B.BF_ERR_INVALID_ARG
     assert B.bf_apply_adjoint(None, 1, 2, 1, 1) == B.BF_ERR_INVALID_ARG

@@ -3,8 +3,6 @@
 FP32 is held to 1e-5 and split BF16 to 1e-4 relative l2 error (the stated
 budgets); split FP16 to 1e-5.  Parity is on identical factors.
 """
-import os
-
 import numpy as np
 import pytest
 
@@ -38,19 +36,14 @@ def _handle(f, prec, kmax=None, cols=None, split=None):
     split the shallowest pass depth whose tiles are shared by wavefront pairs
     (0: none)."""
     from paper_1502_01379_amd import BFHandle
-    env = {"BF_FUSED_KMAX": kmax, "BF_FUSED_COLS": cols, "BF_FUSED_SPLIT": split}
-    old = {k: os.environ.get(k) for k in env}
-    for k, v in env.items():
-        if v is not None:
-            os.environ[k] = str(v)
-    try:
-        h = BFHandle(f, prec)
-    finally:
-        for k, v in old.items():
-            if v is None:
-                os.environ.pop(k, None)
-            else:
-                os.environ[k] = v
+    opts = {}
+    if kmax is not None:
+        opts["fused_kmax"] = kmax
+    if cols is not None:
+        opts["fused_cols"] = cols
+    if split is not None:
+        opts["fused_split"] = split if split > 0 else -1
+    h = BFHandle(f, prec, options=opts)
     assert h.path == 1, "expected the fused MFMA path"
     return h
 
