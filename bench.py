@@ -247,25 +247,116 @@ def bench_shape(args):
     print(json.dumps(out), flush=True)
 
 
-def pass_work(name, L, r, leaf, nrhs, K, has_leaf, has_middle):
-    """Algorithmic flops and compulsory HBM bytes of one fused-pass launch.
+def pass_work(L, r, leaf, nrhs, K, reads_g, writes_u, has_middle):
+    """Algorithmic flops and bytes of one fused-pass launch (its share of the apply).
 
     Unit: one butterfly (a 2r x 2r complex block) applied to one right-hand
     side = (2r)^2 complex multiply-adds = 8 (2r)^2 real flops.  A pass of K
     levels applies K 2^(L-1) of them per column, plus N r multiply-adds per
-    column for a leaf block.  Its compulsory traffic is its input and output
-    activations (P r complex64 per column each), its factor blocks (K 2^(L-1)
-    blocks of (2r)^2 complex64), the leaf blocks (N r complex64) and the
-    middle weights (P r float32).
+    column for a leaf block.  Algorithmic bytes count what the whole apply must
+    move once: the pass's factor blocks (K 2^(L-1) blocks of (2r)^2 complex64),
+    its leaf blocks (N r complex64) and middle weights (P r float32), g if the
+    pass reads it and u if it writes it.  Activations handed from one pass to the
+    next are implementation traffic, not algorithmic.
     """
     P = 2 ** L
     N = P * leaf
+    has_leaf = reads_g or writes_u
     cm = K * (P // 2) * (2 * r) ** 2 + (N * r if has_leaf else 0)
     flops = 8.0 * cm * nrhs
-    act = P * r * 8.0 * nrhs
     fac = K * (P // 2) * (2 * r) ** 2 * 8.0 + (N * r * 8.0 if has_leaf else 0.0)
     mid = P * r * 4.0 if has_middle else 0.0
-    return flops, 2 * act + fac + mid
+    vec = N * 8.0 * nrhs * ((1 if reads_g else 0) + (1 if writes_u else 0))
+    return flops, fac + mid + vec
+
+
+def apply_work(L, r, leaf, nrhs, R=2):
+    """Algorithmic flops and bytes of a whole apply: 2 N r (leaves) + L R r^2 P
+    (butterflies) + P r (middle) complex multiply-adds per column; the factors once
+    (complex64, S as float32) plus g and u once."""
+    P = R ** L
+    N = leaf * P
+    flops = 8.0 * (2 * N * r + L * R * r * r * P + P * r) * nrhs
+    bytes_ = (2 * N * r + L * P * R * r * r) * 8.0 + P * r * 4.0 + 2 * N * 8.0 * nrhs
+    return flops, bytes_
+
+
+def roofline_time(flops, bytes_, prec):
+    """(seconds, bound) of the roofline for MFMA work flops * MFMA_WORK[prec]."""
+    t_mfma = flops * MFMA_WORK[prec] / (PEAK_TFLOPS[prec] * 1e12)
+    t_hbm = bytes_ / (HBM_PEAK_GBS * 1e9)
+    return (t_mfma, "mfma") if t_mfma >= t_hbm else (t_hbm, "hbm")
+
+
+def host_record():
+    """CPU model, core count and BLAS of the host the oracle runs on."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    blas = None
+    try:
+        from threadpoolctl import threadpool_info
+        info = [i for i in threadpool_info() if i.get("user_api") == "blas"]
+        if info:
+            blas = {"library": info[0].get("internal_api"), "version": info[0].get("version"),
+                    "threads": info[0].get("num_threads")}
+    except Exception:
+        pass
+    return {"nproc": os.cpu_count(), "sched_cpus": len(os.sched_getaffinity(0)), "cpu_model": model,
+            "blas": blas}
+
+
+def cpu_oracle_baseline(f, g_host, sample, kern_rows, N):
+    """The FP64 oracle apply of the same factors on a sample of columns: one warm-up
+    run, then the median of three, with BLAS on every core the process may use and
+    on one core; plus the dense apply K[rows, :] g of a few sampled rows (the
+    analogue of the direct evaluation time of Sec. 4).  Returns (baseline, ref):
+    ref is the warm-up result, the FP64 reference of the sampled columns."""
+    import oracle
+    from oracle import kernels
+    from threadpoolctl import threadpool_limits, threadpool_info
+    x = g_host[:, sample].astype(np.complex128)
+    ncores = len(os.sched_getaffinity(0))
+    runs = {}
+    ref = None
+    for label, limit in (("all", ncores), ("one", 1)):
+        with threadpool_limits(limit):
+            threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+            t = time.time()
+            out = oracle.bf_apply(f, x)
+            warm = time.time() - t
+            if ref is None:
+                ref = out
+            ts = []
+            for _ in range(3):
+                t = time.time()
+                oracle.bf_apply(f, x)
+                ts.append(time.time() - t)
+        med = float(np.median(ts))
+        runs[label] = {"value": len(sample) * N / med, "seconds": med, "warmup_seconds": warm,
+                       "threads": threads}
+        print(f"[bench] oracle apply, {label} cores ({threads} threads): {med:.2f} s", file=sys.stderr,
+              flush=True)
+    # dense K[rows, :] g of the 1D FIO of Sec. 4, Example 1, on the sampled columns
+    kern = kernels.fio(N)
+    t = time.time()
+    kernels.dense_apply_rows(kern, kern_rows, x, col_chunk=1 << 16)
+    dense_s = time.time() - t
+    base = {"value": runs["all"]["value"], "unit": "RHS·N/s", "cores": runs["all"]["threads"],
+            "kind": "oracle",
+            "sample": f"FP64 oracle apply of the same factors to {len(sample)} of the columns (N={N}); "
+                      f"median of 3 after a warm-up, BLAS on {runs['all']['threads']} threads",
+            "one_core": runs["one"], "all_cores": runs["all"],
+            "dense_rows": {"rows": int(len(kern_rows)), "columns": len(sample), "seconds": dense_s,
+                           "note": "dense K[rows,:] g of the 1D FIO (Sec. 4 Example 1), FP64, "
+                                   "the analogue of the direct evaluation time"},
+            "host": host_record()}
+    return base, ref
 
 
 def profile_traffic(key):
@@ -346,58 +437,51 @@ def main():
         results[prec]["u_cols"] = u[:, cols].cpu().numpy()
         h.close()
 
-    # oracle: FP64 apply of the same factors on a bounded sample of columns, on one
-    # core; its first three columns are the ones the GPU results are checked on
+    # oracle: FP64 apply of the same factors on a bounded sample of columns (the
+    # three the GPU results are checked on, plus one); BLAS on all cores and on one
     cpu = None
     cols = [0, nrhs // 2, nrhs - 1]
     ref = None
     if not args.no_cpu_baseline:
-        import oracle
-        try:
-            from threadpoolctl import threadpool_limits
-            limiter = threadpool_limits(1)
-        except Exception:
-            limiter = None
-        sample = cols + [c for c in range(1, nrhs) if c not in cols][:max(0, 16 - len(cols))]
-        ncol = len(sample)  # about 10-15 s of one core at N = 2^20
-        t2 = time.time()
-        sub = oracle.bf_apply(f, g_host[:, sample].astype(np.complex128))
-        dt = time.time() - t2
-        if limiter is not None:
-            limiter.unregister()
+        sample = cols + [1]
+        rows = np.random.default_rng(22).choice(N, size=32, replace=False)
+        cpu, sub = cpu_oracle_baseline(f, g_host, sample, rows, N)
         ref = sub[:, :len(cols)]
-        cpu = {"value": ncol * N / dt, "unit": "RHS·N/s", "cores": 1, "kind": "oracle",
-               "sample": f"FP64 oracle apply of the same factors to {ncol} of the {nrhs} columns "
-                         f"(N={N}), {dt:.1f}s, one thread"}
 
-    # roofline of the dominant kernel of the headline precision
+    # roofline of the dominant kernel of the headline precision, from its share of
+    # the apply's algorithmic work, and of the whole apply
     main_res = results[args.precision]
     kt = main_res["kernels"]
     name, (tot_ms, launches) = max(kt.items(), key=lambda kv: kv[1][0])
     avg_ms = tot_ms / max(1, launches)
-    # parse the pass name fused_<side>_l<hi>_<lo>
     parts = name.split("_")            # fused_<H|G>_<fwd|adj>_l<hi>_<lo>
     l_hi, l_lo = int(parts[3][1:]), int(parts[4])
     K = l_hi - l_lo
-    has_leaf = (l_hi == L and parts[1] in ("H", "G"))
-    has_middle = (l_lo == L // 2 and parts[1] == "G")
-    flops, bytes_ = pass_work(name, L, r, leaf, nrhs, K, has_leaf, has_middle)
-    mfma_flops = flops * MFMA_WORK[args.precision]
-    t_mfma = mfma_flops / (PEAK_TFLOPS[args.precision] * 1e12)
-    t_hbm = bytes_ / (HBM_PEAK_GBS * 1e9)
-    if t_mfma >= t_hbm:
-        roof = {"bound": "mfma", "achieved": mfma_flops / (avg_ms * 1e-3) / 1e12,
+    reads_g = l_hi == L and parts[1] == "H"
+    writes_u = l_hi == L and parts[1] == "G"
+    has_middle = l_lo == L // 2 and parts[1] == "G"
+    flops, bytes_ = pass_work(L, r, leaf, nrhs, K, reads_g, writes_u, has_middle)
+    t_roof, bound = roofline_time(flops, bytes_, args.precision)
+    if bound == "mfma":
+        roof = {"bound": "mfma", "achieved": flops * MFMA_WORK[args.precision] / (avg_ms * 1e-3) / 1e12,
                 "peak": PEAK_TFLOPS[args.precision], "unit": "TFLOP/s"}
     else:
         roof = {"bound": "hbm", "achieved": bytes_ / (avg_ms * 1e-3) / 1e9,
                 "peak": HBM_PEAK_GBS, "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
     prec_code = {"f32": 0, "bf16x3": 1, "f16x3": 2}[args.precision]
-    roof["traffic"] = profile_traffic(f"{K},{prec_code},{int(l_hi == L and parts[1] == 'H')},"
-                                      f"{int(l_hi == L and parts[1] == 'G')}")
+    roof["traffic"] = profile_traffic(f"{K},{prec_code},{int(reads_g)},{int(writes_u)}")
     roof["kernel"] = name
     roof["avg_launch_ms"] = avg_ms
     roof["launches"] = launches
+    roof["algorithmic_bytes"] = bytes_
+    roof["algorithmic_flops"] = flops
+    roof["traffic_over_algorithmic"] = roof["traffic"] / bytes_ if roof["traffic"] else None
+    wf, wb = apply_work(L, r, leaf, nrhs)
+    wt, wbound = roofline_time(wf, wb, args.precision)
+    roof["whole_apply"] = {"bound": wbound, "roofline_ms": wt * 1e3, "ms": main_res["ms"],
+                           "frac": wt * 1e3 / main_res["ms"], "algorithmic_bytes": wb,
+                           "algorithmic_flops": wf}
 
     def rel(u_cols):
         if ref is None:
@@ -405,10 +489,17 @@ def main():
         d = u_cols.astype(np.complex128) - ref
         return float(np.sqrt(np.sum(np.abs(d) ** 2) / np.sum(np.abs(ref) ** 2)))
 
+    def rel_max_col(u_cols):
+        if ref is None:
+            return None
+        d = u_cols.astype(np.complex128) - ref
+        return float(np.max(np.sqrt(np.sum(np.abs(d) ** 2, axis=0) / np.sum(np.abs(ref) ** 2, axis=0))))
+
     variants = {}
     for prec, res in results.items():
         variants[prec] = {"value": nrhs * N / (res["ms"] * 1e-3), "ms_per_step": res["ms"],
                           "rel_err_vs_fp64": rel(res["u_cols"]),
+                          "rel_err_max_column": rel_max_col(res["u_cols"]),
                           "kernels_ms_per_launch": {k: v[0] / max(1, v[1]) for k, v in res["kernels"].items()}}
 
     if args.copy_probe:
