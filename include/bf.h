@@ -160,6 +160,23 @@ bf_status bf_apply(bf_handle h, const void *g, void *u, int64_t nrhs, int64_t ld
 bf_status bf_apply_adjoint(bf_handle h, const void *w, void *v, int64_t nrhs, int64_t ld,
                            hipStream_t stream);
 
+/* bf_apply for callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  Same arguments,
+ * kernels and results as bf_apply, but the two activation buffers live in a
+ * scratch array of BF_NOALLOC_SCRATCH_BYTES inside the library (one per GPU,
+ * held until the process ends), so the call allocates nothing, on the device or
+ * the host, and records no profiling events.  The two buffers take
+ * 2 * ceil256(P r ceil(nrhs / C) C * b) bytes (C = 16 columns on the fused path,
+ * 32 otherwise; b = 16 for BF_PREC_F64, 8 otherwise): at N = 65536, r = 16 the
+ * limit holds 64 columns.  A larger nrhs returns BF_ERR_UNSUPPORTED and does
+ * nothing.  Every call on one GPU shares that GPU's array and leaves its last
+ * contents there (no call needs them cleared): calls that overlap on one GPU
+ * (two streams, two threads or two handles) race and must be serialized by the
+ * caller. */
+#define BF_NOALLOC_SCRATCH_BYTES (64u << 20)
+bf_status bf_apply_noalloc(bf_handle h, const void *g, void *u, int64_t nrhs, int64_t ld,
+                           hipStream_t stream);
+
 /* Gradients of a real loss through u = K_BF g.  The paper defines no
  * gradients; this is the chain rule through the factor product of Sec. 1.2,
  * with the complex convention grad = dL/dRe + i dL/dIm.  grad_u = dL/dRe(u) + i dL/dIm(u)

@@ -21,8 +21,9 @@ STATUS_NAMES = ["BF_OK", "BF_ERR_INVALID_ARG", "BF_ERR_SHAPE", "BF_ERR_UNSUPPORT
 PRECISIONS = {"f64": 0, "f32": 1, "bf16x3": 2, "f16x3": 3}
 BF_BWD_RECOMPUTE = 0
 BF_BWD_STORE_ALL = 1
+BF_NOALLOC_SCRATCH_BYTES = 64 << 20
 
-EXPORTED = ["bf_create_from_factors", "bf_create_from_factors_ex", "bf_apply", "bf_apply_adjoint", "bf_backward", "bf_destroy",
+EXPORTED = ["bf_create_from_factors", "bf_create_from_factors_ex", "bf_apply", "bf_apply_noalloc", "bf_apply_adjoint", "bf_backward", "bf_destroy",
             "bf_last_error", "bf_query", "bf_set_profiling", "bf_kernel_times",
             # include/bf_construct.h
             "bf_kernel_entries", "bf_batched_svd", "bf_batched_qr", "bf_batched_column_pivots",
@@ -85,7 +86,7 @@ def load_library(path=LIB_PATH):
     lib.bf_create_from_factors_ex.argtypes = [ctypes.POINTER(BFShape), ctypes.POINTER(BFFactorsHost),
                                               ctypes.c_int, ctypes.POINTER(BFPlanOptions), vp, ctypes.POINTER(vp)]
     lib.bf_create_from_factors_ex.restype = ctypes.c_int
-    for name in ("bf_apply", "bf_apply_adjoint"):
+    for name in ("bf_apply", "bf_apply_adjoint", "bf_apply_noalloc"):
         fn = getattr(lib, name)
         fn.argtypes = [vp, vp, vp, i64, i64, vp]
         fn.restype = ctypes.c_int
@@ -140,6 +141,10 @@ def bf_create_from_factors_ex(shape, factors, precision, options=None, stream=0)
 
 def bf_apply(handle, g, u, nrhs, ld, stream=0):
     return load_library().bf_apply(handle, g, u, nrhs, ld, ctypes.c_void_p(stream))
+
+
+def bf_apply_noalloc(handle, g, u, nrhs, ld, stream=0):
+    return load_library().bf_apply_noalloc(handle, g, u, nrhs, ld, ctypes.c_void_p(stream))
 
 
 def bf_apply_adjoint(handle, w, v, nrhs, ld, stream=0):

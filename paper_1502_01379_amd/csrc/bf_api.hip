@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <thread>
@@ -220,12 +221,18 @@ bf_status check_call(bf_plan *p, const void *in, const void *out, int64_t nrhs, 
   return BF_OK;
 }
 
+// The op list through two ping-pong activation buffers of act_bytes(p, nrhs)
+// each (buf0 == nullptr: the handle's workspace, grown if needed).
 bf_status run_ops(bf_plan *p, const std::vector<LevelOp> &ops, const void *g, void *u,
-                  int64_t nrhs, int64_t ld, hipStream_t s) {
+                  int64_t nrhs, int64_t ld, hipStream_t s, void *buf0 = nullptr, void *buf1 = nullptr) {
   const size_t ab = act_bytes(p, nrhs);
-  bf_status st = ensure_ws(p, 2 * ab);
-  if (st != BF_OK) return st;
-  char *buf[2] = {(char *)p->ws, (char *)p->ws + ab};
+  if (!buf0) {
+    bf_status st = ensure_ws(p, 2 * ab);
+    if (st != BF_OK) return st;
+    buf0 = p->ws;
+    buf1 = (char *)p->ws + ab;
+  }
+  char *buf[2] = {(char *)buf0, (char *)buf1};
   const void *cur = g;
   int which = 0;
   for (size_t t = 0; t < ops.size(); ++t) {
@@ -443,6 +450,72 @@ bf_status bf_apply_adjoint(bf_handle p, const void *w, void *v, int64_t nrhs, in
   return run_ops(p, p->adj_ops, w, v, nrhs, ld, s);
 }
 
+// ---- apply without allocations ------------------------------------------------
+//
+// bf_apply_noalloc runs the same kernels as bf_apply, with its two ping-pong
+// activation buffers in this array instead of the handle's workspace.  The array
+// is a per-GPU object of the library's code (each GPU the library runs on holds
+// its own copy until the process ends); host code reaches its device address only
+// through hipGetSymbolAddress, taken once per device with that device current.
+static __device__ __align__(256) char scratch[BF_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device.
+static bf_status noalloc_scratch(bf_plan *p, void **out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(p, BF_ERR_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices) return fail(p, BF_ERR_UNSUPPORTED, "device ordinal beyond 63");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      return fail(p, BF_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    }
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return BF_OK;
+}
+
+}  // namespace
+
+bf_status bf_apply_noalloc(bf_handle p, const void *g, void *u, int64_t nrhs, int64_t ld,
+                                      hipStream_t s) {
+  if (!p) return fail(nullptr, BF_ERR_INVALID_ARG, "handle is NULL");
+  bf_status st = check_call(p, g, u, nrhs, ld);
+  if (st != BF_OK) return st;
+  const size_t ab = act_bytes(p, nrhs);
+  // two buffers, each starting on a 256-byte boundary
+  const size_t ab_al = (ab + 255) & ~size_t(255);
+  if (2 * ab_al > BF_NOALLOC_SCRATCH_BYTES)
+    return fail(p, BF_ERR_UNSUPPORTED,
+                "bf_apply_noalloc: " + std::to_string(nrhs) + " columns need " + std::to_string(2 * ab_al) +
+                    " bytes of scratch, more than its " + std::to_string((size_t)BF_NOALLOC_SCRATCH_BYTES) +
+                    " bytes; use bf_apply or fewer columns per call");
+  void *base = nullptr;
+  if ((st = noalloc_scratch(p, &base)) != BF_OK) return st;
+  void *buf0 = base, *buf1 = (char *)base + ab_al;
+  // no profiling events: recording them may create events
+  const bool prof = p->profiling;
+  p->profiling = false;
+  if (p->path == 1) {
+    hipError_t e = bfly::fused_run(p, false, g, u, nrhs, ld, buf0, buf1, s);
+    if (e != hipSuccess) st = fail(p, BF_ERR_HIP, std::string("fused apply: ") + hipGetErrorString(e));
+  } else {
+    st = run_ops(p, p->fwd_ops, g, u, nrhs, ld, s, buf0, buf1);
+  }
+  p->profiling = prof;
+  return st;
+}
+
 // Backward pass.  The forward chain is a_0 = (V^L)^* g, a_t = op_t(a_{t-1}) for
 // t = 1 .. 2h+1 (H levels, middle, G levels), u = U^L a_{2h+1}.  Going back, the
 // gradient of op_t needs its input a_{t-1} and the incoming delta_t (the
@@ -468,7 +541,7 @@ namespace {
 // restore the states between them.  The b_k live in a ring of six buffers: an
 // adjoint pass reads one and writes at most five, and the gradients of the
 // levels it mirrors are taken before the next pass.
-bf_status backward_fused(bf_plan *p, const void *g, const void *grad_u, void *grad_g,
+static bf_status backward_fused(bf_plan *p, const void *g, const void *grad_u, void *grad_g,
                          const bf_factor_grads *grads, int64_t nrhs, int64_t ld, bool store_all,
                          hipStream_t s) {
   bf_status st;
