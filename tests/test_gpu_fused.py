@@ -201,24 +201,41 @@ def test_fused_backward_without_grad_g(dev):
     assert oracle.rel_err(grad_g.cpu().numpy(), ref["g"]) < 1e-5
 
 
+def _col_errs(u, ref):
+    d = u.astype(np.complex128) - ref
+    return np.sqrt(np.sum(np.abs(d) ** 2, axis=0) / np.sum(np.abs(ref) ** 2, axis=0))
+
+
 def test_full_size_2_20_256_rhs(dev):
     # N = 2^20, leaf 16, r = 16 (L = 16), 256 right-hand sides; synthetic factors of
-    # the real shapes; every row of three sampled columns is compared with the oracle
+    # the real shapes; every row of three sampled columns is compared with the
+    # oracle, column by column and over all three; the adjoint too on the default
+    # pass plans.
     f = synthetic_factors(2, 16, 16, 16, seed=20)
     N = 1 << 20
     g = complex_gaussian((N, 256), 21, dtype=np.complex64)
     gd = torch.from_numpy(g).to(dev)
     cols = [0, 131, 255]
     ref = oracle.bf_apply(f, g[:, cols].astype(np.complex128))
+    ref_adj = oracle.bf_apply_adjoint(f, g[:, cols].astype(np.complex128))
     for prec, wcols, kmax, split in [("f32", 16, None, None), ("f32", 16, 4, 4),
                                      ("bf16x3", 16, None, None), ("bf16x3", 16, 4, 0),
                                      ("bf16x3", 32, None, None), ("f16x3", 16, None, None)]:
         h = _handle(f, prec, cols=wcols, kmax=kmax, split=split)
         u = h.apply(gd)
         torch.cuda.synchronize()
-        err = oracle.rel_err(u[:, cols].cpu().numpy(), ref)
-        print(f"N=2^20 {prec} wave columns {wcols} kmax {kmax} split {split} rel err {err:.3e}",
-              flush=True)
-        assert err < TOL[prec]
+        uc = u[:, cols].cpu().numpy()
+        err = oracle.rel_err(uc, ref)
+        cerr = _col_errs(uc, ref)
+        print(f"N=2^20 {prec} wave columns {wcols} kmax {kmax} split {split} rel err {err:.3e} "
+              f"per column {cerr.max():.3e}", flush=True)
+        assert err < TOL[prec] and cerr.max() < TOL[prec]
+        if wcols == 16 and kmax is None:
+            v = h.apply_adjoint(gd)
+            torch.cuda.synchronize()
+            verr = _col_errs(v[:, cols].cpu().numpy(), ref_adj)
+            print(f"N=2^20 {prec} adjoint per column {verr.max():.3e}", flush=True)
+            assert verr.max() < TOL[prec]
+            del v
         h.close()
         del u

@@ -118,8 +118,9 @@ def test_backward_matches_oracle_gradient(dev, fio4096, prec):
     h = _handle(f, prec)
     grad_g, grads = h.backward(_to(g, dev, prec), _to(gu, dev, prec))
     assert oracle.rel_err(grad_g.cpu().numpy(), ref["g"]) < TOL[prec]
-    for a, b in zip(_flat_grads(grads, h), _flat_grads(ref, h)):
-        assert oracle.rel_err(a.cpu().numpy(), b) < 10 * TOL[prec]
+    errs = [oracle.rel_err(a.cpu().numpy(), b) for a, b in zip(_flat_grads(grads, h), _flat_grads(ref, h))]
+    print(f"per-level {prec} factor gradient errors: max {max(errs):.3e}", flush=True)
+    assert max(errs) < TOL[prec]
     # keeping every level gives the same numbers as recomputing them
     grad_g2, grads2 = h.backward(_to(g, dev, prec), _to(gu, dev, prec), flags=BF_BWD_STORE_ALL)
     assert torch.equal(grad_g, grad_g2)
@@ -197,8 +198,9 @@ def test_level_mfma_shapes(dev, radix, leaf, L, r, nrhs):
     grad_g, grads = h.backward(_to(g, dev, "f32"), _to(gu, dev, "f32"))
     ref = oracle.bf_grad(f, g, gu)
     assert oracle.rel_err(grad_g.cpu().numpy(), ref["g"]) < TOL["f32"]
-    for a, b in zip(_flat_grads(grads, h), _flat_grads(ref, h)):
-        assert oracle.rel_err(a.cpu().numpy(), b) < 10 * TOL["f32"]
+    errs = [oracle.rel_err(a.cpu().numpy(), b) for a, b in zip(_flat_grads(grads, h), _flat_grads(ref, h))]
+    print(f"per-level MFMA factor gradient errors: max {max(errs):.3e}", flush=True)
+    assert max(errs) < TOL["f32"]
 
 
 @pytest.mark.parametrize("prec", ["f32", "bf16x3"])
