@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--log2n", type=int, default=20)
     ap.add_argument("--nrhs", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--options", default="{}",
+                    help="JSON dict of bf_plan_options fields for the handles (kernel-path variants)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 1 GiB device copy (reference for HBM byte counters)")
     ap.add_argument("--shape", choices=sorted(SHAPES), default=None,
@@ -70,7 +72,7 @@ def bench_backward(args):
     f = synthetic_factors(2, 16, L, 16, seed=30)
     g = torch.from_numpy(complex_gaussian((N, args.nrhs), 31, dtype=np.complex64)).to(dev)
     gu = torch.from_numpy(complex_gaussian((N, args.nrhs), 32, dtype=np.complex64)).to(dev)
-    h = BFHandle(f, args.precision)
+    h = BFHandle(f, args.precision, options=json.loads(args.options))
     modes = {}
     for mode, flags in (("recompute", BF_BWD_RECOMPUTE), ("store_all", BF_BWD_STORE_ALL)):
         for _ in range(args.warmup):
@@ -412,7 +414,7 @@ def main():
     results = {}
     for prec in precisions:
         t1 = time.time()
-        h = BFHandle(f, prec)
+        h = BFHandle(f, prec, options=json.loads(args.options))
         print(f"[bench] {prec}: handle created in {time.time() - t1:.1f}s (path {h.path})",
               file=sys.stderr, flush=True)
         stream = torch.cuda.current_stream()

@@ -174,7 +174,57 @@ def _from_middle(N, R, leaf, L, r, Uh, Vh, S):
             "VL": VL, "UL": UL, "S": S, "H": Hb, "G": Gb}
 
 
-def construct_from_entries(N, radix, leaf, r, entries, q=3, iters=3, seed=0, drop_rel=1e-14):
+def _factor_shapes(N, R, leaf, L, r):
+    h = L // 2
+    P = R ** L
+    return {"radix": R, "leaf": int(leaf), "L": L, "r": int(r),
+            "VL": np.zeros((P, leaf, r), dtype=np.complex128),
+            "UL": np.zeros((P, leaf, r), dtype=np.complex128),
+            "S": np.zeros((R ** h, R ** h, r)),
+            "H": [np.zeros((R ** (l + 1), R ** (L - l - 1), r, R * r), dtype=np.complex128) for l in range(h, L)],
+            "G": [np.zeros((R ** (l + 1), R ** (L - l - 1), r, R * r), dtype=np.complex128) for l in range(h, L)]}
+
+
+def _streamed_from_entries(N, R, leaf, L, r, entries, q, iters, seed, drop_rel):
+    """The O(N log N)-memory order of Sec. 3.3: for one middle node at a time, the
+    blocks of its row (U side) or column (V side) are factorized by Alg. 2.2 and
+    the node's U^h_i (V^h_j) is factorized recursively at once, so only O(N r)
+    values of the middle level exist at any time.  Each block draws from its own
+    stream, so the U and V sides reproduce the same block factorizations."""
+    h = L // 2
+    m = R ** h
+    b = N // m
+    lv = L - h
+    f = _factor_shapes(N, R, leaf, L, r)
+    per_node = (R ** L) // m                        # leaves below one middle node
+
+    def block(i, j):
+        rng = np.random.default_rng([seed, i, j])
+        rows, cols = i * b, j * b
+        U0, s, V0h = _sampled_block(lambda I, J: entries(rows + I, cols + J), b, r, rng, q, iters)
+        return _first_form(U0, s, V0h, drop_rel)
+
+    nt = min(_threads(), m) if b >= 256 else 1
+    with _one_blas_thread(), ThreadPoolExecutor(nt) as ex:
+        for side in ("U", "V"):
+            for a in range(m):
+                pairs = [(a, j) for j in range(m)] if side == "U" else [(i, a) for i in range(m)]
+                W = np.zeros((1, m, b, r), dtype=np.complex128)
+                for k, (U, V, S) in enumerate(ex.map(lambda ij: block(*ij), pairs)):
+                    W[0, k] = U if side == "U" else V
+                    if side == "U":
+                        f["S"][a, k] = S
+                blocks, leaves = _recursive(W, R, r, lv)
+                dst = f["G"] if side == "U" else f["H"]
+                for t in range(lv):
+                    n_t = R ** (t + 1)
+                    dst[t][a * n_t:(a + 1) * n_t] = blocks[t]
+                (f["UL"] if side == "U" else f["VL"])[a * per_node:(a + 1) * per_node] = leaves
+    return f
+
+
+def construct_from_entries(N, radix, leaf, r, entries, q=3, iters=3, seed=0, drop_rel=1e-14,
+                           streamed=None):
     """Canonical factors of K from its entries (the second case of Sec. 3.1).
 
     entries(rows, cols) returns the dense submatrix K[rows][:, cols] (FP64 complex)
@@ -182,11 +232,20 @@ def construct_from_entries(N, radix, leaf, r, entries, q=3, iters=3, seed=0, dro
     by randomized sampling (Alg. 2.2), with its own random stream, so the result
     does not depend on the order the blocks are processed in; the blocks are
     spread over threads, and the recursion of Sec. 3.2 is batched over every node.
+
+    streamed: True factorizes one middle node at a time (Sec. 3.3: working memory
+    O(N r) instead of the 2 N^(3/2) r / leaf^(1/2) values of U^h and V^h, at twice the
+    middle-level work); None (default) streams when U^h and V^h would take more than
+    4 GB.  Both orders give the same factors.
     """
     R = int(radix)
     L = _depth(N, leaf, R)
     m = R ** (L // 2)
     b = N // m
+    if streamed is None:
+        streamed = 2 * m * m * b * r * 16 > 4e9
+    if streamed:
+        return _streamed_from_entries(N, R, leaf, L, r, entries, q, iters, seed, drop_rel)
     Uh = np.zeros((m, m, b, r), dtype=np.complex128)
     Vh = np.zeros((m, m, b, r), dtype=np.complex128)
     S = np.zeros((m, m, r))

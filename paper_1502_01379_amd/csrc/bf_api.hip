@@ -605,6 +605,13 @@ static bf_status backward_fused(bf_plan *p, const void *g, const void *grad_u, v
                bfly::fused_run_pass(p, FP[j], in, out, lvl, nrhs, ld, s));
     return BF_OK;
   };
+  // recompute mode: the last forward pass leaves the states inside it in the
+  // buffers the recomputation would fill, so the first adjoint pass needs no
+  // second run of it
+  if (!store_all && np > 0) {
+    const bfly::PassShape sl = bfly::fused_pass_shape(FP[np - 1]);
+    for (int d = 1; d < sl.K; ++d) aptr[td0[np - 1] + d] = buf(seg0 + d - 1);
+  }
   for (int j = 0; j < np; ++j)
     if ((st = run_forward(j, false)) != BF_OK) return st;
 
@@ -615,7 +622,7 @@ static bf_status backward_fused(bf_plan *p, const void *g, const void *grad_u, v
   for (int i = 0; i < np; ++i) {
     const int j = np - 1 - i;  // the forward pass over the same levels
     const bfly::PassShape fs = bfly::fused_pass_shape(FP[j]);
-    if (!store_all) {
+    if (!store_all && j != np - 1) {
       for (int d = 1; d < fs.K; ++d) aptr[td0[j] + d] = buf(seg0 + d - 1);
       if ((st = run_forward(j, true)) != BF_OK) return st;
     }

@@ -18,6 +18,14 @@
 #include "bf_construct.h"
 #include "bf_internal.h"
 
+// Index and value checks of the host build that runs these kernels on the CPU
+// (BF_CONSTRUCT_HOST_CHECK); nothing in the library build.
+#ifdef BF_CONSTRUCT_HOST_CHECK
+#define BFC_ASSERT(c) SIMT_CHECK((c), #c)
+#else
+#define BFC_ASSERT(c) ((void)0)
+#endif
+
 namespace {
 
 // ---- complex helpers (double2 = (re, im)) --------------------------------------
@@ -57,6 +65,9 @@ __device__ __forceinline__ double block_sum(double v, double *red4) {
 
 inline unsigned grid_for(int64_t total, int threads = 256) {
   int64_t g = (total + threads - 1) / threads;
+#ifdef BF_CONSTRUCT_HOST_CHECK
+  g = std::min<int64_t>(g, 4);  // host check: few workgroups, the loops stride over the rest
+#endif
   return (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, 65536));
 }
 
@@ -115,6 +126,9 @@ __global__ __launch_bounds__(256) void k_entries(EntArgs a) {
     }
     const int64_t i = row0 + (a.rl ? a.rl[z * a.rls + u] : u);
     const int64_t k = col0 + (a.cl ? a.cl[z * a.cls + v] : v);
+    BFC_ASSERT(!a.rl || (a.rl[z * a.rls + u] >= 0 && (a.m == 0 || a.rl[z * a.rls + u] < a.b)));
+    BFC_ASSERT(!a.cl || (a.cl[z * a.cls + v] >= 0 && (a.m == 0 || a.cl[z * a.cls + v] < a.b)));
+    BFC_ASSERT(i >= 0 && i < a.N && k >= 0 && k < a.N);
     double2 val = kernel_entry(a.kind, a.N, i, k);
     if (a.conj) val.y = -val.y;
     a.out[z * a.bs + x * a.ld + y] = val;
@@ -157,6 +171,8 @@ __global__ __launch_bounds__(64) void k_sample(SampArgs a) {
   int64_t *o = a.out + z * a.ostride;
   for (int64_t t = 0; t < a.nkeep; ++t) {
     const int64_t v = a.keep[z * a.kstride + t];
+    BFC_ASSERT(v >= 0 && v < a.dim);
+    BFC_ASSERT(!(used[v >> 5] >> (v & 31) & 1u));  // the kept indices are distinct
     o[t] = v;
     used[v >> 5] |= 1u << (v & 31);
   }
@@ -180,6 +196,7 @@ __global__ __launch_bounds__(64) void k_sample(SampArgs a) {
     used[v >> 5] |= 1u << (v & 31);
     o[a.nkeep + got++] = v;
   }
+  BFC_ASSERT(got == want);
 }
 
 // ---- column pivots of a pivoted QR (Algorithm 2.2, steps 2 and 3) ------------------
@@ -214,6 +231,7 @@ __global__ __launch_bounds__(256) void k_colpiv(PivArgs a) {
     const double2 *col = A + (int64_t)j * p;
     double s = 0.0;
     for (int t = lane; t < p; t += 64) s += cabs2(col[t]);
+    BFC_ASSERT(std::isfinite(s));
     s = wave_sum(s);
     if (lane == 0) nrm[j] = s;
   }
@@ -249,6 +267,7 @@ __global__ __launch_bounds__(256) void k_colpiv(PivArgs a) {
           b0 = bv[w];
           i0 = bi[w];
         }
+      BFC_ASSERT(i0 >= 0 && i0 < n);
       if (i0 < 0 || i0 >= n) i0 = n - 1;  // only reachable with non-finite entries
       pick = i0;
       a.piv[blockIdx.x * (int64_t)a.npiv + k] = i0;
@@ -317,6 +336,7 @@ __global__ __launch_bounds__(256) void k_cgs_qr(QrArgs a) {
   for (int l = 0; l < k; ++l) {
     double s = 0.0;
     for (int64_t row = tid; row < n; row += 256) s += cabs2(A[row * k + l]);
+    BFC_ASSERT(std::isfinite(s));
     const double n0 = block_sum(s, red4);
     if (tid < k) rsum[tid] = make_double2(0.0, 0.0);
     __syncthreads();
@@ -417,6 +437,7 @@ __global__ __launch_bounds__(256) void k_jacobi_svd(SvdArgs a) {
   for (int e = tid; e < m * n; e += 256) {
     const int x = e / n, y = e - x * n;
     const double2 v = A[e];
+    BFC_ASSERT(std::isfinite(v.x) && std::isfinite(v.y));
     Ac[y * MM + x] = v;
     mx = fmax(mx, fmax(fabs(v.x), fabs(v.y)));
   }
@@ -591,6 +612,7 @@ __global__ __launch_bounds__(256) void k_gather_rows(GatherArgs a) {
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t z = e / per, rem = e - z * per, t = rem / a.ncol, y = rem - t * a.ncol;
+    BFC_ASSERT(a.idx[z * a.ibs + t] >= 0 && a.idx[z * a.ibs + t] < a.sbs / a.sld);
     a.dst[z * a.dbs + rem] = a.src[z * a.sbs + a.idx[z * a.ibs + t] * a.sld + y];
   }
 }

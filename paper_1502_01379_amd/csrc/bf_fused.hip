@@ -527,7 +527,7 @@ bf_status fused_build_backward(bf_plan *p, hipStream_t s) {
         const PassSide side = sd == 0 ? (adj ? kGadj : kHfwd) : (adj ? kHadj : kGfwd);
         fp->K = K;
         fp->cols = 16;
-        fp->split = K >= 4;
+        fp->split = K >= 3 && K >= (p->opt.fused_split < 0 ? 99 : p->opt.fused_split > 0 ? p->opt.fused_split : 4);
         fp->log_slo = L - l_hi;
         fp->mode_si = (side == kHfwd || side == kGadj) ? 1 : 0;
         fp->in_kind = t == 0 ? (sd == 0 ? kInUser : kInMiddle) : kInAct;

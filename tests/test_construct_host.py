@@ -102,3 +102,17 @@ def test_entries_seed_fixes_the_result():
     b = construct_from_entries(256, 2, 4, 8, kern.entries, seed=1)
     for key in ("VL", "UL", "S"):
         assert np.array_equal(a[key], b[key])
+
+
+@pytest.mark.parametrize("radix,N,leaf,r", [(2, 4096, 16, 16), (4, 1024, 4, 8), (2, 1024, 1, 6)])
+def test_streamed_order_gives_the_same_factors(radix, N, leaf, r):
+    # Sec. 3.3: one middle node at a time (U side by rows, V side by columns, every
+    # block from its own random stream) reproduces the all-at-once factors exactly
+    from paper_1502_01379_amd.construct import construct_from_entries
+    kern = kernels.fio(N) if radix == 2 else kernels.grt2d(int(round(N ** 0.5)))
+    a = construct_from_entries(N, radix, leaf, r, kern.entries, seed=5, streamed=False)
+    b = construct_from_entries(N, radix, leaf, r, kern.entries, seed=5, streamed=True)
+    for key in ("VL", "UL", "S"):
+        assert np.array_equal(a[key], b[key]), key
+    for t in range(len(a["G"])):
+        assert np.array_equal(a["G"][t], b["G"][t]) and np.array_equal(a["H"][t], b["H"][t]), t
