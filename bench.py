@@ -29,7 +29,10 @@ if ROOT not in sys.path:
 METRIC = "BF apply RHS·N/s at stated rel. err (FP32 vs split-BF16 vs FP64); % roofline"
 HBM_PEAK_GBS = 8000.0
 PEAK_TFLOPS = {"f32": 157.3, "bf16x3": 2516.6, "f16x3": 2516.6}   # dense MFMA, per dtype
-MFMA_WORK = {"f32": 1.0, "bf16x3": 3.0, "f16x3": 3.0}              # MFMA products per algorithmic one
+# real MFMA work per algorithmic flop (8 per complex multiply-add): FP32 forms each
+# complex block product from three real products (Gauss), split precisions from
+# three products per real product
+MFMA_WORK = {"f32": 0.75, "bf16x3": 3.0, "f16x3": 3.0}
 
 
 def parse():

@@ -10,7 +10,8 @@
 //        grad[2 hi + cx][lo][rx][cy r + ry] = sum_n X[strided(b,cx)][rx][n] conj(Y[contig(b,cy)][ry][n]),
 //    (grad_B = sum_n d_out x_in^* for G levels with X = d_out, Y = x_in;
 //     grad_W = sum_n x_in d_out^* for H levels with X = x_in, Y = d_out),
-//    as a 32 x 32 x (2 nrhs) real contraction on the matrix cores.  One
+//    as three 32 x 32 x nrhs real contractions on the matrix cores (Gauss's
+//    three-product form of the complex sum).  One
 //    wavefront per butterfly, columns in chunks of 16 staged through LDS
 //    (transposed, padded rows: conflict-free reads), fixed summation order.
 #include <hip/hip_runtime.h>
@@ -91,11 +92,12 @@ __global__ void k_pack_pass(PackPassArgs a, float *__restrict__ out, int split) 
     o16[((4 + w) * 64 + lane) * 8 + j] = lo16;
     return;
   }
+  // FP32: Re M and +Im M, for Gauss's three products (block16_f32)
   const int T = f >> 4, sidx = f & 15;
   const int part = sidx >> 3, cp = (sidx >> 2) & 1, rho = sidx & 3;
   const float v = block_value(static_cast<const float2 *>(pd.Fb), b / blo, b % blo, blo, pd.tconj,
                               16 * T + i, 16 * cp + 4 * e + rho, part);
-  out[bi * 2048 + ((f >> 2) * 64 + lane) * 4 + (f & 3)] = v;
+  out[bi * 2048 + ((f >> 2) * 64 + lane) * 4 + (f & 3)] = part ? -v : v;
 }
 
 // Leaf pairs of a pass (tile, q: leaves (tile << K) + 2q + c) as two 16 x 16 FP32
@@ -127,7 +129,7 @@ __global__ void k_pack_leaf16(const float2 *__restrict__ W, float *__restrict__ 
     o16[((c * 2 + 1) * 64 + lane) * 8 + jv] = lo;
     return;
   }
-  out[bi * 1024 + ((c * 2 + pc) * 64 + lane) * 4 + jj] = v;
+  out[bi * 1024 + ((c * 2 + pc) * 64 + lane) * 4 + jj] = pc ? -v : v;  // FP32: +Im (Gauss)
 }
 
 constexpr int kRowPad = 272;  // bytes per column of a staged 32-row chunk (256 + 16)
@@ -200,7 +202,7 @@ __global__ __launch_bounds__(256) void k_grad_leaf(const float2 *__restrict__ U,
   if (pr >= npairs) return;
   char *lx = lds[wave][0], *ly = lds[wave][1];
   const int i = lane & 31, eta = lane >> 5;
-  floatx16 dre = {}, dim = {};
+  floatx16 t1 = {}, t2 = {}, t3 = {};
   const int64_t npad = ((nrhs + 15) >> 4) << 4;
   for (int64_t n0 = 0; n0 < npad; n0 += 16) {
     stage_user(U, ld, 2 * pr * kR, n0, nrhs, lx, lane);
@@ -212,10 +214,10 @@ __global__ __launch_bounds__(256) void k_grad_leaf(const float2 *__restrict__ U,
       const int n = 8 * eta + s;
       const f32x2 xv = *reinterpret_cast<const f32x2 *>(lx + n * kRowPad + i * 8);
       const f32x2 yv = *reinterpret_cast<const f32x2 *>(ly + n * kRowPad + i * 8);
-      dre = __builtin_amdgcn_mfma_f32_32x32x2f32(xv.x, yv.x, dre, 0, 0, 0);
-      dre = __builtin_amdgcn_mfma_f32_32x32x2f32(xv.y, yv.y, dre, 0, 0, 0);
-      dim = __builtin_amdgcn_mfma_f32_32x32x2f32(xv.y, yv.x, dim, 0, 0, 0);
-      dim = __builtin_amdgcn_mfma_f32_32x32x2f32(-xv.x, yv.y, dim, 0, 0, 0);
+      // x conj(y) by Gauss's three products, as in k_grad_level
+      t1 = __builtin_amdgcn_mfma_f32_32x32x2f32(xv.x, yv.x, t1, 0, 0, 0);
+      t2 = __builtin_amdgcn_mfma_f32_32x32x2f32(xv.y, yv.y, t2, 0, 0, 0);
+      t3 = __builtin_amdgcn_mfma_f32_32x32x2f32(xv.x + xv.y, yv.x - yv.y, t3, 0, 0, 0);
     }
     __builtin_amdgcn_wave_barrier();
   }
@@ -225,8 +227,8 @@ __global__ __launch_bounds__(256) void k_grad_leaf(const float2 *__restrict__ U,
     const int c = row >> 4;
     if ((i >> 4) != c) continue;  // only the two diagonal 16 x 16 blocks
     float2 v;
-    v.x = dre[reg];
-    v.y = dim[reg];
+    v.x = t1[reg] + t2[reg];
+    v.y = t3[reg] - t1[reg] + t2[reg];
     grad[((2 * pr + c) * kR + (row & 15)) * kR + (i & 15)] = v;
   }
 }
@@ -245,7 +247,7 @@ __global__ __launch_bounds__(256) void k_grad_level(const float2 *__restrict__ X
   const int64_t sy0 = hi * 2 * blo + 2 * lo, sy1 = sy0 + 1;      // contiguous slots
   char *lx = lds[wave][0], *ly = lds[wave][1];
   const int i = lane & 31, eta = lane >> 5;
-  floatx16 dre = {}, dim = {};
+  floatx16 t1 = {}, t2 = {}, t3 = {};
   const int64_t npad = ((nrhs + 15) >> 4) << 4;
   // the next chunk's loads are in flight while the current one is contracted
   Chunk cx, cy;
@@ -265,11 +267,12 @@ __global__ __launch_bounds__(256) void k_grad_level(const float2 *__restrict__ X
       const int n = 8 * eta + s;
       const f32x2 xv = *reinterpret_cast<const f32x2 *>(lx + n * kRowPad + i * 8);
       const f32x2 yv = *reinterpret_cast<const f32x2 *>(ly + n * kRowPad + i * 8);
-      // columns past nrhs hold zeros in every activation buffer
-      dre = __builtin_amdgcn_mfma_f32_32x32x2f32(xv.x, yv.x, dre, 0, 0, 0);
-      dre = __builtin_amdgcn_mfma_f32_32x32x2f32(xv.y, yv.y, dre, 0, 0, 0);
-      dim = __builtin_amdgcn_mfma_f32_32x32x2f32(xv.y, yv.x, dim, 0, 0, 0);
-      dim = __builtin_amdgcn_mfma_f32_32x32x2f32(-xv.x, yv.y, dim, 0, 0, 0);
+      // columns past nrhs hold zeros in every activation buffer; x conj(y) by Gauss's
+      // three products: t1 = Re x Re y, t2 = Im x Im y, t3 = (Re x + Im x)(Re y - Im y),
+      // Re = t1 + t2, Im = t3 - t1 + t2
+      t1 = __builtin_amdgcn_mfma_f32_32x32x2f32(xv.x, yv.x, t1, 0, 0, 0);
+      t2 = __builtin_amdgcn_mfma_f32_32x32x2f32(xv.y, yv.y, t2, 0, 0, 0);
+      t3 = __builtin_amdgcn_mfma_f32_32x32x2f32(xv.x + xv.y, yv.x - yv.y, t3, 0, 0, 0);
     }
     __builtin_amdgcn_wave_barrier();
   }
@@ -279,8 +282,8 @@ __global__ __launch_bounds__(256) void k_grad_level(const float2 *__restrict__ X
     const int row = 8 * (reg >> 2) + 4 * eta + (reg & 3);
     const int cx = row >> 4, rx = row & 15;
     float2 v;
-    v.x = dre[reg];
-    v.y = dim[reg];
+    v.x = t1[reg] + t2[reg];
+    v.y = t3[reg] - t1[reg] + t2[reg];
     grad[(((2 * hi + cx) * blo + lo) * kR + rx) * (2 * kR) + i] = v;
   }
 }

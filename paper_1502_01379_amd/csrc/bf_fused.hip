@@ -68,12 +68,13 @@ float pack_block(const cd *M, int prec, int cols, char *dst) {
           out[((s >> 2) * 64 + lane) * 4 + (s & 3)] =
               (float)aval(i, s >> 4, (s >> 3) & 1, row32(e, s & 7));
       } else {
+        // 16-column FP32 products use Gauss's three products: Re M and +Im M
         const int i = lane & 15, e = lane >> 4;
         for (int T = 0; T < 2; ++T)
           for (int s = 0; s < 16; ++s) {
             const int f = 16 * T + s;
-            out[((f >> 2) * 64 + lane) * 4 + (f & 3)] =
-                (float)aval(16 * T + i, s >> 3, (s >> 2) & 1, 4 * e + (s & 3));
+            const double v = aval(16 * T + i, s >> 3, (s >> 2) & 1, 4 * e + (s & 3));
+            out[((f >> 2) * 64 + lane) * 4 + (f & 3)] = (float)((s >> 3) ? -v : v);
           }
       }
     }
@@ -129,11 +130,14 @@ float pack_leaf16(const cd *M, int prec, char *dst) {
     return (j >> 2) == 0 ? v.real() : -v.imag();
   };
   if (prec == kF32) {
+    // Gauss's three products (leaf16_f32): Re M_c and +Im M_c
     float *out = reinterpret_cast<float *>(dst);
     for (int c = 0; c < 2; ++c)
       for (int lane = 0; lane < 64; ++lane)
-        for (int j = 0; j < 8; ++j)
-          out[((c * 2 + (j >> 2)) * 64 + lane) * 4 + (j & 3)] = (float)aval(c, lane & 15, j, lane >> 4);
+        for (int j = 0; j < 8; ++j) {
+          const double v = aval(c, lane & 15, j, lane >> 4);
+          out[((c * 2 + (j >> 2)) * 64 + lane) * 4 + (j & 3)] = (float)((j >> 2) ? -v : v);
+        }
     return 1.f;
   }
   double mx = 0;

@@ -243,38 +243,43 @@ __device__ __forceinline__ void block32_split(const BlockA &A, float bscale, con
 // ---- COLS = 16: slot = x[8] (4 real parts, 4 imaginary parts) -------------------
 //
 // Output tile T (16 rows) is output slot c = T.
-// FP32, v_mfma_f32_16x16x4_f32: K step s = 8 part + 4 c' + rho takes row 4e + rho
-// of input slot c'; A value for lane (i, e): [Re M, -Im M][16T + i][that K index],
-// stored at float index 16 T + s of the lane's 32.
+// FP32, v_mfma_f32_16x16x4_f32, three real products per complex product (Gauss):
+// with a = Re M, b = Im M, x = Re in, y = Im in,
+//   P1 = a x,  P2 = b y,  P3 = (a + b)(x + y);   Re out = P1 - P2,  Im out = P3 - P1 - P2.
+// K step k = 4 c' + rho takes row 4e + rho of input slot c'; the lane's A values for
+// output row 16 T + i are Re M at float 16 T + k and Im M at float 16 T + 8 + k of
+// its 32.
 // Split, v_mfma_f32_16x16x32: K step t = part; this lane's 8 values are rows
-// 4e..4e+3 of slot 0 then of slot 1; A.v[2T + t] hi, A.v[4 + 2T + t] lo.
-__device__ __forceinline__ void block16_f32(const BlockA &A, const float *x0, const float *x1,
+// 4e..4e+3 of slot 0 then of slot 1; A.v[2T + t] hi, A.v[4 + 2T + t] lo (of
+// [Re M, -Im M]).
+// The block is read from LDS (blk: its packed 8 KB) one output slot at a time, so
+// only half of it and three accumulators are live.
+__device__ __forceinline__ void block16_f32(const char *blk, int lane, const float *x0, const float *x1,
                                             float *y0, float *y1) {
-  floatx4 dr[2] = {{}, {}}, di[2] = {{}, {}};
 #pragma unroll
-  for (int s = 0; s < 16; ++s) {
-    const int part = s >> 3, cp = (s >> 2) & 1, rho = s & 3;
-    const float *x = cp ? x1 : x0;
-    const float xre = x[rho], xim = x[4 + rho];
+  for (int T = 0; T < 2; ++T) {
+    // keep the compiler from hoisting the second half's operands (it spills then)
+    __builtin_amdgcn_sched_barrier(0);
+    u32x4 av[4];
 #pragma unroll
-    for (int T = 0; T < 2; ++T) {
-      const int f = 16 * T + s;
-      const float a = as_f32(A.v[f >> 2], f & 3);
-      if (part == 0) {
-        dr[T] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, xre, dr[T], 0, 0, 0);
-        di[T] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, xim, di[T], 0, 0, 0);
-      } else {
-        dr[T] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, xim, dr[T], 0, 0, 0);
-        di[T] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, -xre, di[T], 0, 0, 0);
-      }
+    for (int j = 0; j < 4; ++j) av[j] = reinterpret_cast<const u32x4 *>(blk + (4 * T + j) * 1024)[lane];
+    floatx4 p1 = {}, p2 = {}, p3 = {};
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int cp = k >> 2, rho = k & 3;
+      const float *x = cp ? x1 : x0;
+      const float xre = x[rho], xim = x[4 + rho];
+      const float a = as_f32(av[k >> 2], k & 3), b = as_f32(av[2 + (k >> 2)], k & 3);
+      p1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a, xre, p1, 0, 0, 0);
+      p2 = __builtin_amdgcn_mfma_f32_16x16x4f32(b, xim, p2, 0, 0, 0);
+      p3 = __builtin_amdgcn_mfma_f32_16x16x4f32(a + b, xre + xim, p3, 0, 0, 0);
     }
-  }
+    float *y = T ? y1 : y0;
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    y0[v] = dr[0][v];
-    y0[4 + v] = di[0][v];
-    y1[v] = dr[1][v];
-    y1[4 + v] = di[1][v];
+    for (int v = 0; v < 4; ++v) {
+      y[v] = p1[v] - p2[v];
+      y[4 + v] = p3[v] - p1[v] - p2[v];
+    }
   }
 }
 
@@ -337,9 +342,7 @@ __device__ __forceinline__ void block_op(const BlockA &A, float bscale, const fl
     else
       block32_split<halfx8, _Float16, true>(A, bscale, x0, x1, y0, y1);
   } else {
-    if constexpr (PREC == kF32)
-      block16_f32(A, x0, x1, y0, y1);
-    else if constexpr (PREC == kBF16)
+    if constexpr (PREC == kBF16)
       block16_split<bf16x8, __bf16, false>(A, 1.f, x0, x1, y0, y1);
     else
       block16_split<halfx8, _Float16, true>(A, bscale, x0, x1, y0, y1);
@@ -384,24 +387,22 @@ __device__ __forceinline__ void leaf16_split(const u32x4 ahi_u, const u32x4 alo_
   }
 }
 
+// FP32 leaf block, Gauss's three products as in block16_f32: a0 holds Re M, a1 Im M
+// of this lane's K index rho (rows 4e + rho).
 __device__ __forceinline__ void leaf16_f32(const u32x4 a0, const u32x4 a1, const float *x, float *y) {
-  floatx4 dr = {}, di = {};
+  floatx4 p1 = {}, p2 = {}, p3 = {};
 #pragma unroll
-  for (int s = 0; s < 8; ++s) {
-    const float a = as_f32(s < 4 ? a0 : a1, s & 3);
-    const int rho = s & 3;
-    if (s < 4) {
-      dr = __builtin_amdgcn_mfma_f32_16x16x4f32(a, x[rho], dr, 0, 0, 0);
-      di = __builtin_amdgcn_mfma_f32_16x16x4f32(a, x[4 + rho], di, 0, 0, 0);
-    } else {
-      dr = __builtin_amdgcn_mfma_f32_16x16x4f32(a, x[4 + rho], dr, 0, 0, 0);
-      di = __builtin_amdgcn_mfma_f32_16x16x4f32(a, -x[rho], di, 0, 0, 0);
-    }
+  for (int rho = 0; rho < 4; ++rho) {
+    const float a = as_f32(a0, rho), b = as_f32(a1, rho);
+    const float xre = x[rho], xim = x[4 + rho];
+    p1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a, xre, p1, 0, 0, 0);
+    p2 = __builtin_amdgcn_mfma_f32_16x16x4f32(b, xim, p2, 0, 0, 0);
+    p3 = __builtin_amdgcn_mfma_f32_16x16x4f32(a + b, xre + xim, p3, 0, 0, 0);
   }
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    y[v] = dr[v];
-    y[4 + v] = di[v];
+    y[v] = p1[v] - p2[v];
+    y[4 + v] = p3[v] - p1[v] - p2[v];
   }
 }
 
@@ -611,6 +612,8 @@ void k_fused_pass(FusedArgs a) {
     const char *blk = lds + (sti & 1) * (HB * kBlockBytes) + (beta % HB) * kBlockBytes;
     if constexpr (COLS == 16 && is_leaf_group<K, LI, LO>(g)) {
       leaf_pair16<PREC>(blk, lane, block_scale(g, beta), x0, x1, y0, y1);
+    } else if constexpr (COLS == 16 && PREC == kF32) {
+      block16_f32(blk, lane, x0, x1, y0, y1);
     } else {
       BlockA A;
       static_for<8>([&](auto V) {
@@ -850,6 +853,8 @@ void k_fused_pass_x2(FusedArgs a) {
     const char *blk = lds + (sti & 1) * (HB * kBlockBytes) + (half * PB + bw % PB) * kBlockBytes;
     if constexpr (is_leaf_group<K, LI, LO>(g)) {
       leaf_pair16<PREC>(blk, lane, block_scale(g, half * WB + bw), x0, x1, y0, y1);
+    } else if constexpr (PREC == kF32) {
+      block16_f32(blk, lane, x0, x1, y0, y1);
     } else {
       BlockA A;
       static_for<8>([&](auto V) {
