@@ -28,11 +28,13 @@ if ROOT not in sys.path:
 
 METRIC = "BF apply RHS·N/s at stated rel. err (FP32 vs split-BF16 vs FP64); % roofline"
 HBM_PEAK_GBS = 8000.0
-PEAK_TFLOPS = {"f32": 157.3, "bf16x3": 2516.6, "f16x3": 2516.6}   # dense MFMA, per dtype
-# real MFMA work per algorithmic flop (8 per complex multiply-add): FP32 forms each
-# complex block product from three real products (Gauss), split precisions from
-# three products per real product
-MFMA_WORK = {"f32": 0.75, "bf16x3": 3.0, "f16x3": 3.0}
+PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16x3": 2516.6, "f16x3": 2516.6}   # dense MFMA, per dtype
+# real MFMA work per algorithmic flop (8 per complex multiply-add): FP64 and FP32
+# form each complex block product from three real products (Gauss), split
+# precisions from three products per real product
+MFMA_WORK = {"f64": 0.75, "f32": 0.75, "bf16x3": 3.0, "f16x3": 3.0}
+# bytes of one complex value of the vectors and factors
+CPLX_BYTES = {"f64": 16.0, "f32": 8.0, "bf16x3": 8.0, "f16x3": 8.0}
 
 
 def parse():
@@ -40,8 +42,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--precision", default="bf16x3", choices=["bf16x3", "f32", "f16x3"])
-    ap.add_argument("--variants", default="f32", help="comma list of extra precisions to time")
+    ap.add_argument("--precision", default="bf16x3", choices=["bf16x3", "f32", "f16x3", "f64"])
+    ap.add_argument("--variants", default="f32,f64", help="comma list of extra precisions to time")
     ap.add_argument("--log2n", type=int, default=20)
     ap.add_argument("--nrhs", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -252,7 +254,7 @@ def bench_shape(args):
     print(json.dumps(out), flush=True)
 
 
-def pass_work(L, r, leaf, nrhs, K, reads_g, writes_u, has_middle):
+def pass_work(L, r, leaf, nrhs, K, reads_g, writes_u, has_middle, cb=8.0):
     """Algorithmic flops and bytes of one fused-pass launch (its share of the apply).
 
     Unit: one butterfly (a 2r x 2r complex block) applied to one right-hand
@@ -261,28 +263,30 @@ def pass_work(L, r, leaf, nrhs, K, reads_g, writes_u, has_middle):
     column for a leaf block.  Algorithmic bytes count what the whole apply must
     move once: the pass's factor blocks (K 2^(L-1) blocks of (2r)^2 complex64),
     its leaf blocks (N r complex64) and middle weights (P r float32), g if the
-    pass reads it and u if it writes it.  Activations handed from one pass to the
-    next are implementation traffic, not algorithmic.
+    pass reads it and u if it writes it (cb bytes per complex value: 8, or 16 for
+    FP64, whose real values take 8).  Activations handed from one pass to the next
+    are implementation traffic, not algorithmic.
     """
     P = 2 ** L
     N = P * leaf
     has_leaf = reads_g or writes_u
     cm = K * (P // 2) * (2 * r) ** 2 + (N * r if has_leaf else 0)
     flops = 8.0 * cm * nrhs
-    fac = K * (P // 2) * (2 * r) ** 2 * 8.0 + (N * r * 8.0 if has_leaf else 0.0)
-    mid = P * r * 4.0 if has_middle else 0.0
-    vec = N * 8.0 * nrhs * ((1 if reads_g else 0) + (1 if writes_u else 0))
+    fac = K * (P // 2) * (2 * r) ** 2 * cb + (N * r * cb if has_leaf else 0.0)
+    mid = P * r * cb / 2 if has_middle else 0.0
+    vec = N * cb * nrhs * ((1 if reads_g else 0) + (1 if writes_u else 0))
     return flops, fac + mid + vec
 
 
-def apply_work(L, r, leaf, nrhs, R=2):
+def apply_work(L, r, leaf, nrhs, R=2, cb=8.0):
     """Algorithmic flops and bytes of a whole apply: 2 N r (leaves) + L R r^2 P
     (butterflies) + P r (middle) complex multiply-adds per column; the factors once
-    (complex64, S as float32) plus g and u once."""
+    (cb bytes per complex entry: complex64, or complex128 for FP64; S real of half
+    that) plus g and u once."""
     P = R ** L
     N = leaf * P
     flops = 8.0 * (2 * N * r + L * R * r * r * P + P * r) * nrhs
-    bytes_ = (2 * N * r + L * P * R * r * r) * 8.0 + P * r * 4.0 + 2 * N * 8.0 * nrhs
+    bytes_ = (2 * N * r + L * P * R * r * r) * cb + P * r * cb / 2 + 2 * N * cb * nrhs
     return flops, bytes_
 
 
@@ -409,13 +413,15 @@ def main():
     t0 = time.time()
     f = synthetic_factors(2, leaf, L, r, seed=20)
     g_host = complex_gaussian((N, nrhs), 21, dtype=np.complex64)
-    g = torch.from_numpy(g_host).to(dev)
-    u = torch.empty_like(g)
+    g32 = torch.from_numpy(g_host).to(dev)
     print(f"[bench] inputs ready in {time.time() - t0:.1f}s (N={N}, nrhs={nrhs})", file=sys.stderr, flush=True)
 
     precisions = [args.precision] + [p for p in args.variants.split(",") if p and p != args.precision]
     results = {}
     for prec in precisions:
+        # FP64 handles take complex128 vectors (the same values)
+        g = g32.to(torch.complex128) if prec == "f64" else g32
+        u = torch.empty_like(g)
         t1 = time.time()
         h = BFHandle(f, prec, options=json.loads(args.options))
         print(f"[bench] {prec}: handle created in {time.time() - t1:.1f}s (path {h.path})",
@@ -441,6 +447,7 @@ def main():
         cols = [0, nrhs // 2, nrhs - 1]
         results[prec]["u_cols"] = u[:, cols].cpu().numpy()
         h.close()
+        del g, u
 
     # oracle: FP64 apply of the same factors on a bounded sample of columns (the
     # three the GPU results are checked on, plus one); BLAS on all cores and on one
@@ -465,7 +472,7 @@ def main():
     reads_g = l_hi == L and parts[1] == "H"
     writes_u = l_hi == L and parts[1] == "G"
     has_middle = l_lo == L // 2 and parts[1] == "G"
-    flops, bytes_ = pass_work(L, r, leaf, nrhs, K, reads_g, writes_u, has_middle)
+    flops, bytes_ = pass_work(L, r, leaf, nrhs, K, reads_g, writes_u, has_middle, cb=CPLX_BYTES[args.precision])
     t_roof, bound = roofline_time(flops, bytes_, args.precision)
     if bound == "mfma":
         roof = {"bound": "mfma", "achieved": flops * MFMA_WORK[args.precision] / (avg_ms * 1e-3) / 1e12,
@@ -474,7 +481,7 @@ def main():
         roof = {"bound": "hbm", "achieved": bytes_ / (avg_ms * 1e-3) / 1e9,
                 "peak": HBM_PEAK_GBS, "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    prec_code = {"f32": 0, "bf16x3": 1, "f16x3": 2}[args.precision]
+    prec_code = {"f32": 0, "bf16x3": 1, "f16x3": 2, "f64": 3}[args.precision]
     roof["traffic"] = profile_traffic(f"{K},{prec_code},{int(reads_g)},{int(writes_u)}")
     roof["kernel"] = name
     roof["avg_launch_ms"] = avg_ms
@@ -482,7 +489,7 @@ def main():
     roof["algorithmic_bytes"] = bytes_
     roof["algorithmic_flops"] = flops
     roof["traffic_over_algorithmic"] = roof["traffic"] / bytes_ if roof["traffic"] else None
-    wf, wb = apply_work(L, r, leaf, nrhs)
+    wf, wb = apply_work(L, r, leaf, nrhs, cb=CPLX_BYTES[args.precision])
     wt, wbound = roofline_time(wf, wb, args.precision)
     roof["whole_apply"] = {"bound": wbound, "roofline_ms": wt * 1e3, "ms": main_res["ms"],
                            "frac": wt * 1e3 / main_res["ms"], "algorithmic_bytes": wb,
@@ -502,9 +509,13 @@ def main():
 
     variants = {}
     for prec, res in results.items():
+        vf, vb = apply_work(L, r, leaf, nrhs, cb=CPLX_BYTES[prec])
+        vt, vbound = roofline_time(vf, vb, prec)
         variants[prec] = {"value": nrhs * N / (res["ms"] * 1e-3), "ms_per_step": res["ms"],
                           "rel_err_vs_fp64": rel(res["u_cols"]),
                           "rel_err_max_column": rel_max_col(res["u_cols"]),
+                          "whole_apply_roofline": {"bound": vbound, "roofline_ms": vt * 1e3,
+                                                   "frac": vt * 1e3 / res["ms"]},
                           "kernels_ms_per_launch": {k: v[0] / max(1, v[1]) for k, v in res["kernels"].items()}}
 
     if args.copy_probe:
@@ -526,10 +537,10 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"bf16x3": "bf16", "f16x3": "f16", "f32": "f32"}[args.precision],
+        "dtype": {"bf16x3": "bf16", "f16x3": "f16", "f32": "f32", "f64": "f64"}[args.precision],
         "precision": {"bf16x3": "split BF16: hi*hi + hi*lo + lo*hi MFMA products, FP32 accumulation",
                       "f16x3": "split FP16: three MFMA products, FP32 accumulation, power-of-two scaling",
-                      "f32": "FP32 MFMA"}[args.precision],
+                      "f32": "FP32 MFMA", "f64": "FP64 MFMA"}[args.precision],
         "rel_err_vs_fp64": variants[args.precision]["rel_err_vs_fp64"],
         "data": "synthetic",
         "config": {"workload": f"1D FIO-shaped butterfly factorization, N=2^{args.log2n}, leaf 16 "

@@ -128,13 +128,15 @@ bf_status bf_create_from_factors(const bf_shape *shape, const bf_factors_host *f
  * agree to within the precision's tolerance. */
 typedef struct {
   int32_t path;         /* 0: fused MFMA passes where the shape allows them (radix 2, */
-                        /*    leaf 16, r 16, not FP64), else per-level kernels;        */
+                        /*    leaf 16, r 16), else per-level kernels;                  */
                         /* 1: per-level kernels (FP64 and FP32 only)                   */
-  int32_t fused_cols;   /* fused passes: columns per wavefront, 0 (= 16) or 32          */
+  int32_t fused_cols;   /* fused passes: columns per wavefront, 0 (= 16) or 32; FP64   */
+                        /* passes have 16 (32 sends FP64 handles to per-level kernels) */
   int32_t fused_kmax;   /* fused passes: deepest pass in levels, 0 = 4 (16 columns) or  */
                         /* 3 (32 columns); 1 .. that maximum                            */
   int32_t fused_split;  /* fused passes: passes of at least this many levels share a   */
-                        /* tile between two wavefronts; 0 = 4, -1 = never              */
+                        /* tile between two wavefronts; 0 = 4, -1 = never (FP64 passes */
+                        /* of three or four levels always share their tiles)           */
   int32_t level_mfma;   /* per-level FP32 butterflies with R r in {32, 64, 128}:        */
                         /* 0 = on the matrix cores, -1 = one thread per output value    */
   int32_t level_ksplit; /* R r = 128 on the matrix cores: 0 = K range split over two    */
@@ -189,8 +191,9 @@ bf_status bf_apply_noalloc(bf_handle h, const void *g, void *u, int64_t nrhs, in
  * BF_BWD_RECOMPUTE (the default 0) only some of them are kept (the pass
  * boundaries on the fused path, every fourth level otherwise) and the others
  * are recomputed inside the call; BF_BWD_STORE_ALL keeps all 2h + 2 of them
- * (more workspace, less work).  Both modes give identical results.  On the fused
- * path the backward passes compute in split BF16 for BF_PREC_SPLIT_BF16 handles
+ * (more workspace, less work).  Both modes give identical results.  FP64 handles
+ * take the per-level kernels in FP64 on either path.  On the fused path the
+ * backward passes compute in split BF16 for BF_PREC_SPLIT_BF16 handles
  * and in FP32 otherwise (gradient sums in FP32); its first call on a handle also
  * packs copies of the blocks in that precision (device memory owned by the
  * handle, about the size of the packed factors).  The workspace

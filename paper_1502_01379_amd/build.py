@@ -17,7 +17,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libbfly.so")
-SOURCES = ["bf_api.hip", "bf_simple.hip", "bf_level.hip", "bf_bwd.hip", "bf_fused.hip", "bf_fused_f32.hip", "bf_fused_bf16.hip", "bf_fused_f16.hip", "bf_construct.hip"]
+SOURCES = ["bf_api.hip", "bf_simple.hip", "bf_level.hip", "bf_bwd.hip", "bf_fused.hip", "bf_fused_f32.hip", "bf_fused_bf16.hip", "bf_fused_f16.hip", "bf_fused_f64.hip", "bf_construct.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 DEVICE_FLAGS = [

@@ -672,7 +672,8 @@ bf_status bf_backward(bf_handle p, const void *g, const void *grad_u, void *grad
   }
   if (flags & ~BF_BWD_STORE_ALL) return fail(p, BF_ERR_INVALID_ARG, "unknown flags");
   const bool store_all = (flags & BF_BWD_STORE_ALL) != 0;
-  if (p->path == 1 && p->cs == 4)
+  // FP64 handles take the per-level backward on either path
+  if (p->path == 1 && p->cs == 4 && p->prec != BF_PREC_F64)
     return backward_fused(p, g, grad_u, grad_g, grads, nrhs, ld, store_all, s);
 
   // per-level kernels: the forward chain level by level, every kc-th activation

@@ -169,6 +169,35 @@ float pack_leaf16(const cd *M, int prec, char *dst) {
   return bscale;
 }
 
+// FP64 block for k_fused_pass_f64 (Gauss's three products): lane i + 16e holds
+// M[16T + i][16c' + 4 rho + e] (K step k = 4c' + rho) at double
+// (((2T + part) 4 + k / 2) 64 + lane) 2 + k % 2; part 0: Re M, part 1: Im M.
+void pack_block64(const cd *M, char *dst) {
+  double *out = reinterpret_cast<double *>(dst);
+  for (int T = 0; T < 2; ++T)
+    for (int part = 0; part < 2; ++part)
+      for (int k = 0; k < 8; ++k)
+        for (int lane = 0; lane < 64; ++lane) {
+          const int i = lane & 15, e = lane >> 4;
+          const cd v = M[(16 * T + i) * 32 + 16 * (k >> 2) + 4 * (k & 3) + e];
+          out[(((2 * T + part) * 4 + k / 2) * 64 + lane) * 2 + (k & 1)] = part ? v.imag() : v.real();
+        }
+}
+
+// FP64 leaf pair: the diagonal 16 x 16 blocks M_c[i][k] = M[16c + i][16c + k];
+// lane i + 16e holds M_c[i][4 rho + e] at double (((2c + part) 2 + rho / 2) 64 + lane) 2 + rho % 2.
+void pack_leaf64(const cd *M, char *dst) {
+  double *out = reinterpret_cast<double *>(dst);
+  for (int c = 0; c < 2; ++c)
+    for (int part = 0; part < 2; ++part)
+      for (int rho = 0; rho < 4; ++rho)
+        for (int lane = 0; lane < 64; ++lane) {
+          const int i = lane & 15, e = lane >> 4;
+          const cd v = M[(16 * c + i) * 32 + 16 * c + 4 * rho + e];
+          out[(((2 * c + part) * 2 + rho / 2) * 64 + lane) * 2 + (rho & 1)] = part ? v.imag() : v.real();
+        }
+}
+
 }  // namespace
 
 struct FusedPass {
@@ -178,6 +207,7 @@ struct FusedPass {
   void *fac = nullptr, *leaf = nullptr;
   float *fscale = nullptr, *lscale = nullptr;
   const float *Sm = nullptr;
+  const double *Sm64 = nullptr;  // FP64 passes
   std::string name;
   std::vector<void *> owned;
 };
@@ -310,7 +340,7 @@ bf_status upload(bf_plan *p, FusedPass *fp, const void *src, size_t bytes, void 
 }
 
 bf_status build_pass(bf_plan *p, const HostFactors &F, const PassPlan &pp, int prec, int cols,
-                     const float *Sm, FusedPass **out) {
+                     const void *Sm, FusedPass **out) {
   FusedPass *fp = new FusedPass();
   *out = fp;
   const int K = pp.K, L = p->L;
@@ -322,13 +352,17 @@ bf_status build_pass(bf_plan *p, const HostFactors &F, const PassPlan &pp, int p
   fp->in_kind = pp.in_kind;
   fp->out_kind = pp.out_kind;
   fp->ntiles = int64_t(1) << (L - K);
-  fp->Sm = Sm;
+  if (prec == kF64)
+    fp->Sm64 = static_cast<const double *>(Sm);
+  else
+    fp->Sm = static_cast<const float *>(Sm);
+  const int64_t bbytes = prec == kF64 ? kBlockBytes64 : kBlockBytes;
   static const char *side_name[] = {"H_fwd", "G_fwd", "G_adj", "H_adj"};
   fp->name = std::string("fused_") + side_name[pp.side] + "_l" + std::to_string(pp.l_hi) + "_" +
              std::to_string(pp.l_lo);
   const int64_t ntiles = fp->ntiles;
   const int64_t nblk = (int64_t)K * ntiles * NB;
-  std::vector<char> buf((size_t)nblk * kBlockBytes);
+  std::vector<char> buf((size_t)(nblk * bbytes));
   std::vector<float> sc((size_t)nblk, 1.f);
   parallel_for(ntiles, [&](int64_t tile) {
     std::vector<cd> M(1024);
@@ -339,7 +373,10 @@ bf_status build_pass(bf_plan *p, const HostFactors &F, const PassPlan &pp, int p
           const int beta = ap * (1 << d) + b;
           const int64_t bi = ((int64_t)d * ntiles + tile) * NB + beta;
           butterfly_block(F, pp, d, hi, lo, ap, b, M.data());
-          sc[bi] = pack_block(M.data(), prec, cols, buf.data() + bi * kBlockBytes);
+          if (prec == kF64)
+            pack_block64(M.data(), buf.data() + bi * bbytes);
+          else
+            sc[bi] = pack_block(M.data(), prec, cols, buf.data() + bi * bbytes);
         }
   });
   bf_status st = upload(p, fp, buf.data(), buf.size(), &fp->fac);
@@ -351,7 +388,7 @@ bf_status build_pass(bf_plan *p, const HostFactors &F, const PassPlan &pp, int p
     // last pass: leaf out (U forward, V adjoint)
     const bool in = pp.in_kind == kInUser;
     const bool use_v = in ? (pp.side == kHfwd) : (pp.side == kHadj);
-    const int64_t lbytes = cols == 16 ? kBlockBytes / 2 : kBlockBytes;
+    const int64_t lbytes = prec == kF64 ? kLeafBytes64 : cols == 16 ? kBlockBytes / 2 : kBlockBytes;
     std::vector<char> lb((size_t)(ntiles * NB * lbytes));
     std::vector<float> ls((size_t)ntiles * NB, 1.f);
     parallel_for(ntiles, [&](int64_t tile) {
@@ -359,8 +396,11 @@ bf_status build_pass(bf_plan *p, const HostFactors &F, const PassPlan &pp, int p
       for (int q = 0; q < NB; ++q) {
         const int64_t bi = tile * NB + q;
         leaf_block(F, use_v, in, (tile << K) + 2 * q, M.data());
-        ls[bi] = cols == 16 ? pack_leaf16(M.data(), prec, lb.data() + bi * lbytes)
-                            : pack_block(M.data(), prec, cols, lb.data() + bi * lbytes);
+        if (prec == kF64)
+          pack_leaf64(M.data(), lb.data() + bi * lbytes);
+        else
+          ls[bi] = cols == 16 ? pack_leaf16(M.data(), prec, lb.data() + bi * lbytes)
+                              : pack_block(M.data(), prec, cols, lb.data() + bi * lbytes);
       }
     });
     st = upload(p, fp, lb.data(), lb.size(), &fp->leaf);
@@ -380,6 +420,7 @@ FusedArgs pass_args(const bf_plan *p, const FusedPass *fp, const void *in, void 
   a.fscale = fp->fscale;
   a.lscale = fp->lscale;
   a.Sm = fp->Sm;
+  a.Sm64 = fp->Sm64;
   a.ld = ld;
   a.nrhs = nrhs;
   a.nchunks = (nrhs + fp->cols - 1) / fp->cols;
@@ -401,6 +442,7 @@ hipError_t launch_pass(const bf_plan *p, const FusedPass *fp, const void *in, vo
                        int64_t nrhs, int64_t ld, hipStream_t s) {
   FusedArgs a = pass_args(p, fp, in, out, nrhs, ld);
   const bool li = fp->in_kind == kInUser, lo = fp->out_kind == kOutUser;
+  if (p->prec == BF_PREC_F64) return launch_f64(a, fp->K, li, lo, s);
   if (p->prec == BF_PREC_F32) return launch_prec<kF32>(a, fp->cols, fp->K, li, lo, fp->split, s);
   if (p->prec == BF_PREC_SPLIT_BF16)
     return launch_prec<kBF16>(a, fp->cols, fp->K, li, lo, fp->split, s);
@@ -411,14 +453,15 @@ hipError_t launch_pass(const bf_plan *p, const FusedPass *fp, const void *in, vo
 
 bool fused_supported(const bf_shape &sh, bf_precision prec, const bf_plan_options &opt) {
   if (opt.path == 1) return false;
-  return prec != BF_PREC_F64 && sh.radix == 2 && sh.leaf == kRank && sh.r == kRank && sh.L >= 2;
+  if (prec == BF_PREC_F64 && opt.fused_cols == 32) return false;  // FP64 passes: 16 columns only
+  return sh.radix == 2 && sh.leaf == kRank && sh.r == kRank && sh.L >= 2;
 }
 
 bf_status fused_build(bf_plan *p, const bf_factors_host *f) {
   HostFactors F{f, p->L, p->h};
   // wavefront geometry (columns per wavefront) and deepest pass (the handle's
   // options can select other variants, for comparisons)
-  const int cols = p->opt.fused_cols == 32 ? 32 : kDefaultCols;
+  const int cols = p->opt.fused_cols == 32 && p->prec != BF_PREC_F64 ? 32 : kDefaultCols;
   const int kcap = cols == 32 ? 3 : 4;
   // four-level passes (four passes per apply at L = 16) for every precision
   const int kmax = p->opt.fused_kmax > 0 ? std::min(kcap, p->opt.fused_kmax) : kcap;
@@ -426,22 +469,32 @@ bf_status fused_build(bf_plan *p, const bf_factors_host *f) {
   // between a pair of wavefronts
   const int split_min = p->opt.fused_split < 0 ? 99 : p->opt.fused_split > 0 ? p->opt.fused_split : 4;
   p->cs = cols == 32 ? 5 : 4;
-  const int prec = p->prec == BF_PREC_F32 ? kF32 : p->prec == BF_PREC_SPLIT_BF16 ? kBF16 : kF16;
+  const int prec = p->prec == BF_PREC_F64 ? kF64
+                   : p->prec == BF_PREC_F32 ? kF32
+                   : p->prec == BF_PREC_SPLIT_BF16 ? kBF16 : kF16;
 
-  // middle weights as FP32 in natural slot order: S for the forward, S^T for the adjoint
+  // middle weights in natural slot order (FP64 for FP64 passes, FP32 otherwise):
+  // S for the forward, S^T for the adjoint
   const int64_t m = p->m;
-  std::vector<float> S((size_t)m * m * kRank), ST((size_t)m * m * kRank);
+  const size_t wb = prec == kF64 ? 8 : 4;
+  std::vector<char> S((size_t)m * m * kRank * wb), ST((size_t)m * m * kRank * wb);
   for (int64_t i = 0; i < m; ++i)
     for (int64_t j = 0; j < m; ++j)
       for (int k = 0; k < kRank; ++k) {
-        const float v = (float)f->S[(i * m + j) * kRank + k];
-        S[(i * m + j) * kRank + k] = v;
-        ST[(j * m + i) * kRank + k] = v;
+        const double v = f->S[(i * m + j) * kRank + k];
+        const size_t a = (size_t)((i * m + j) * kRank + k), b = (size_t)((j * m + i) * kRank + k);
+        if (prec == kF64) {
+          reinterpret_cast<double *>(S.data())[a] = v;
+          reinterpret_cast<double *>(ST.data())[b] = v;
+        } else {
+          reinterpret_cast<float *>(S.data())[a] = (float)v;
+          reinterpret_cast<float *>(ST.data())[b] = (float)v;
+        }
       }
   FusedPass holder;
   void *dS = nullptr, *dST = nullptr;
-  bf_status st = upload(p, &holder, S.data(), S.size() * 4, &dS);
-  if (st == BF_OK) st = upload(p, &holder, ST.data(), ST.size() * 4, &dST);
+  bf_status st = upload(p, &holder, S.data(), S.size(), &dS);
+  if (st == BF_OK) st = upload(p, &holder, ST.data(), ST.size(), &dST);
   for (void *d : holder.owned) p->allocs.push_back(d);
   if (st != BF_OK) return st;
 
@@ -467,7 +520,7 @@ bf_status fused_build(bf_plan *p, const bf_factors_host *f) {
       PassPlan pp{adj ? kHadj : kGfwd, K, l_lo + K, l_lo, t == 0 ? kInMiddle : kInAct,
                   t + 1 == ks.size() ? kOutUser : kOutAct};
       FusedPass *fp = nullptr;
-      st = build_pass(p, F, pp, prec, cols, t == 0 ? (const float *)(adj ? dST : dS) : nullptr, &fp);
+      st = build_pass(p, F, pp, prec, cols, t == 0 ? (adj ? dST : dS) : nullptr, &fp);
       list.push_back(fp);
       if (fp) fp->split = cols == 16 && fp->K >= 3 && fp->K >= split_min;
       if (st != BF_OK) return st;

@@ -59,11 +59,13 @@ typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kRank = 16;          // r == n0 == 16
 constexpr int kBlockBytes = 8192;  // packed A operands of one 32 x 32 complex block
+constexpr int kBlockBytes64 = 16384;  // the same, FP64 (Re M and Im M as doubles)
+constexpr int kLeafBytes64 = 8192;    // FP64 leaf pair (two 16 x 16 blocks)
 constexpr int kDefaultCols = 16;   // columns per wavefront unless BF_FUSED_COLS says otherwise
 
 enum InKind : int { kInAct = 0, kInUser = 1, kInMiddle = 2 };
 enum OutKind : int { kOutAct = 0, kOutUser = 1 };
-enum Prec : int { kF32 = 0, kBF16 = 1, kF16 = 2 };
+enum Prec : int { kF32 = 0, kBF16 = 1, kF16 = 2, kF64 = 3 };
 
 struct FusedArgs {
   const void *in;
@@ -73,6 +75,7 @@ struct FusedArgs {
   const float *fscale;  // FP16: power-of-two scale per block, same order as fac
   const float *lscale;  // FP16: same for leaf blocks
   const float *Sm;      // middle weights in natural slot order (kInMiddle)
+  const double *Sm64;   // the same in FP64 (FP64 passes)
   int64_t ld, nrhs, nchunks, nslots, ntiles, m;
   int log_slo, mode_si, in_kind, out_kind, ngroups, log_m;
   // optional per-depth copies of the state in the activation layout (used by the
@@ -1012,6 +1015,8 @@ inline int64_t waves_per_group(const FusedArgs &a) {
 template <int PREC>
 hipError_t launch_prec(FusedArgs a, int cols, int K, bool leaf_in, bool leaf_out, bool split,
                        hipStream_t s);
+// Launch one FP64 pass (bf_fused_f64.hip; 16 columns per wavefront, K <= 4).
+hipError_t launch_f64(FusedArgs a, int K, bool leaf_in, bool leaf_out, hipStream_t s);
 
 #define BF_FUSED_LAUNCH(COLS, KK, PREC, LI, LO)                                               \
   do {                                                                                        \
