@@ -36,19 +36,30 @@ namespace fused {
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
+#ifndef BF_F64_MAX_CHUNKS
 #define BF_F64_MAX_CHUNKS 2
+#endif
+#ifndef BF_F64_STAGE_BUFFERS
+#define BF_F64_STAGE_BUFFERS 2
+#endif
 
-template <int K>
+// CW column chunks per workgroup; blocks stream through NBUF LDS stage buffers,
+// NBUF - 1 stages ahead of the one being computed.
+template <int K, int CW, int NBUF>
 struct F64Traits {
   static constexpr int kW = K >= 3 ? 2 : 1;                 // wavefronts per tile of one chunk
   static constexpr int kHS = (1 << K) / kW;                 // slots per wavefront
   static constexpr int kWB = kHS / 2;                       // blocks per wavefront per level
-  static constexpr int kMaxWaves = BF_F64_MAX_CHUNKS * kW;  // wavefronts per workgroup
+  static constexpr int kWaves = CW * kW;                    // wavefronts per workgroup
   static constexpr int kStageBytes = kW * kBlockBytes64;    // one block per wavefront position
   static constexpr int kSlotBytes = 4096;                   // one slot of one wavefront (64 x 8 doubles)
-  static constexpr int kSwapBytes = kW == 2 ? kMaxWaves * kSlotBytes : 0;  // one slot per wavefront per round
-  static constexpr int kLdsBytes = 2 * kStageBytes + kSwapBytes;
+  static constexpr int kSwapBytes = kW == 2 ? kWaves * kSlotBytes : 0;  // one slot per wavefront per round
+  static constexpr int kLdsBytes = NBUF * kStageBytes + kSwapBytes;
 };
+
+// s_waitcnt immediate (gfx9 encoding): at most vm vector-memory operations of this
+// wavefront outstanding, no LDS operation outstanding, any export count.
+constexpr int waitcnt_vm(int vm) { return (vm & 15) | (7 << 4) | ((vm >> 4) << 14); }
 
 // Block beta of group g (leaf-in, levels 0 .. K-1, leaf-out).
 template <int K, bool LI>
@@ -132,20 +143,28 @@ __device__ __forceinline__ void leaf_pair_f64(const char *blk, int lane, const d
 
 // Activations (FP64): [chunk][slot][row 16][column 16] complex128; user vectors
 // g, u: [N][ld] complex128.
-template <int K, bool LI, bool LO>
-__global__ __launch_bounds__(F64Traits<K>::kMaxWaves * 64) __attribute__((amdgpu_waves_per_eu(2)))
+template <int K, bool LI, bool LO, int CW, int NBUF>
+__global__ __launch_bounds__((F64Traits<K, CW, NBUF>::kWaves * 64)) __attribute__((amdgpu_waves_per_eu(2)))
 void k_fused_pass_f64(FusedArgs a) {
-  using T = F64Traits<K>;
-  constexpr int W = T::kW, HS = T::kHS, WB = T::kWB;
+  using T = F64Traits<K, CW, NBUF>;
+  constexpr int W = T::kW, HS = T::kHS, WB = T::kWB, NW = T::kWaves;
   constexpr int NST = ((LI ? 1 : 0) + K + (LO ? 1 : 0)) * WB;
+  // global -> LDS loads of one wavefront for stage s (16 or 8 pieces of 1 KB per
+  // block, spread over the workgroup's NW wavefronts), and those of the stages
+  // after sti that are in flight when stage sti begins
+  constexpr auto loads_of = [](int s) { return (is_leaf_group<K, LI, LO>(s / WB) ? 8 : 16) * W / NW; };
+  constexpr auto pending = [loads_of](int sti) {
+    int n = 0;
+    for (int s = sti + 1; s <= sti + NBUF - 2 && s < NST; ++s) n += loads_of(s);
+    return n;
+  };
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform per wavefront
   const int half = W == 2 ? (wave & 1) : 0;
   const int n = lane & 15, e = lane >> 4;
   int64_t tile, group;
   tile_of_block(a, tile, group);
-  const int nw = (int)(blockDim.x >> 6);
-  const int64_t chunk = group * (nw / W) + wave / W;
+  const int64_t chunk = group * CW + wave / W;
   const bool active = chunk < a.nchunks;
   const int64_t slo = int64_t(1) << a.log_slo;
   const int64_t hi = tile >> a.log_slo, lo = tile & (slo - 1);
@@ -155,20 +174,22 @@ void k_fused_pass_f64(FusedArgs a) {
   const int qh = half * HS;  // first tile slot of this wavefront
 
   // stage sti = (group g, block bw): block half WB + bw of group g for both halves,
-  // at position half of its LDS buffer
+  // at position half of LDS buffer sti % NBUF
   __shared__ __attribute__((aligned(16))) char lds[T::kLdsBytes];
-  auto issue_stage = [&](int sti) {
-    char *dst = lds + (sti & 1) * T::kStageBytes;
-    const int g = sti / WB, bw = sti - (sti / WB) * WB;
-    const int lp = is_leaf_group<K, LI, LO>(g) ? kLeafBytes64 / 1024 : kBlockBytes64 / 1024;
-    for (int c = wave; c < W * lp; c += nw) {
+  auto issue_stage = [&](auto STI) {
+    constexpr int sti = STI;
+    char *dst = lds + (sti % NBUF) * T::kStageBytes;
+    constexpr int g = sti / WB, bw = sti % WB;
+    constexpr int lp = is_leaf_group<K, LI, LO>(g) ? kLeafBytes64 / 1024 : kBlockBytes64 / 1024;
+    static_for<loads_of(sti)>([&](auto I) {
+      const int c = wave + (int)I * NW;
       const int pos = c / lp, piece = c - pos * lp;
       const char *src = block64<K, LI>(a, tile, g, pos * WB + bw) + piece * 1024 + lane * 16;
       __builtin_amdgcn_global_load_lds(
           src, (__attribute__((address_space(3))) void *)(dst + pos * kBlockBytes64 + piece * 1024), 16, 0, 0);
-    }
+    });
   };
-  issue_stage(0);
+  issue_stage(std::integral_constant<int, 0>{});
 
   double st[HS][8];
 
@@ -215,24 +236,30 @@ void k_fused_pass_f64(FusedArgs a) {
       });
     });
   }
+  // the next NBUF - 2 stages follow the state loads, so the first stage's wait
+  // leaves them in flight
+  static_for<NBUF - 2>([&](auto I) {
+    if constexpr (1 + (int)I < NST) issue_stage(std::integral_constant<int, 1 + (int)I>{});
+  });
 
   // block half WB + bw of group g, staged in LDS
   auto step = [&](auto GG, auto BW, const double *x0, const double *x1, double *y0, double *y1) {
     constexpr int g = GG, bw = BW;
     constexpr int sti = g * WB + bw;
-    const char *blk = lds + (sti & 1) * T::kStageBytes + half * kBlockBytes64;
+    const char *blk = lds + (sti % NBUF) * T::kStageBytes + half * kBlockBytes64;
     if constexpr (is_leaf_group<K, LI, LO>(g))
       leaf_pair_f64(blk, lane, x0, x1, y0, y1);
     else
       block16_f64(blk, lane, x0, x1, y0, y1);
   };
-  // entering stage sti: its blocks have landed, every wavefront is done with
-  // stage sti - 1, whose buffer now receives stage sti + 1
+  // entering stage sti: its blocks have landed (only the loads of the stages after
+  // it may still be in flight; loads complete in order), every wavefront is done
+  // with stage sti - 1, whose buffer now receives stage sti + NBUF - 1
   auto stage_begin = [&](auto STI) {
     constexpr int sti = STI;
-    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_s_waitcnt(waitcnt_vm(pending(sti)));
     __syncthreads();
-    if constexpr (sti + 1 < NST) issue_stage(sti + 1);
+    if constexpr (sti + NBUF - 1 < NST) issue_stage(std::integral_constant<int, sti + NBUF - 1>{});
   };
   // leaf blocks: slots 2 bw, 2 bw + 1 of this wavefront
   auto pair_group = [&](auto GG) {
@@ -276,7 +303,7 @@ void k_fused_pass_f64(FusedArgs a) {
     // by wavefront 1); each wavefront keeps the operand it holds for its own blocks
     // and sends the other one through LDS, one slot per round
     constexpr int gl = (LI ? 1 : 0) + K - 1;
-    char *const swap = lds + 2 * T::kStageBytes;
+    char *const swap = lds + NBUF * T::kStageBytes;
     double kp[WB][8], rv[WB][8];
     static_for<WB>([&](auto KK) {
       constexpr int k = KK;
@@ -343,13 +370,24 @@ void k_fused_pass_f64(FusedArgs a) {
   });
 }
 
-#define BF_F64_LAUNCH(KK, LI, LO)                                                                \
-  do {                                                                                           \
-    using T = F64Traits<KK>;                                                                     \
-    const int64_t cw = a.nchunks < BF_F64_MAX_CHUNKS ? a.nchunks : BF_F64_MAX_CHUNKS;            \
-    a.ngroups = (int)((a.nchunks + cw - 1) / cw);                                                \
-    hipLaunchKernelGGL((k_fused_pass_f64<KK, LI, LO>), dim3((unsigned)(a.ntiles * a.ngroups)),   \
-                       dim3((unsigned)(cw * T::kW * 64)), 0, s, a);                              \
+template <int K, bool LI, bool LO, int CW>
+void launch_f64_cw(FusedArgs a, hipStream_t s) {
+  constexpr int NBUF = CW >= 4 ? BF_F64_STAGE_BUFFERS : 2;
+  using T = F64Traits<K, CW, NBUF>;
+  a.ngroups = (int)((a.nchunks + CW - 1) / CW);
+  hipLaunchKernelGGL((k_fused_pass_f64<K, LI, LO, CW, NBUF>), dim3((unsigned)(a.ntiles * a.ngroups)),
+                     dim3((unsigned)(T::kWaves * 64)), 0, s, a);
+}
+
+// chunks per workgroup: the most that the column count fills
+#define BF_F64_LAUNCH(KK, LI, LO)                                                     \
+  do {                                                                                \
+    if (BF_F64_MAX_CHUNKS >= 4 && a.nchunks >= 4)                                     \
+      launch_f64_cw<KK, LI, LO, (BF_F64_MAX_CHUNKS >= 4 ? 4 : 1)>(a, s);              \
+    else if (a.nchunks >= 2)                                                          \
+      launch_f64_cw<KK, LI, LO, 2>(a, s);                                             \
+    else                                                                              \
+      launch_f64_cw<KK, LI, LO, 1>(a, s);                                             \
   } while (0)
 
 #define BF_F64_CASES(KK)                 \
