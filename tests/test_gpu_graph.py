@@ -24,6 +24,7 @@ def dev():
     (4, 16, 4, 32, "f32", 40),       # per-level butterflies on the matrix cores
     (2, 16, 8, 16, "bf16x3", 70),    # fused split-tile passes
     (2, 16, 6, 16, "f32", 33),       # fused one-wavefront passes
+    (2, 16, 8, 16, "f64", 40),       # fused FP64 passes (wavefront pairs)
 ])
 def test_apply_replays_in_a_graph(dev, radix, leaf, L, r, prec, nrhs):
     from paper_1502_01379_amd import BFHandle

@@ -37,7 +37,7 @@ def _noalloc(h, g, nrhs, ld):
 
 @pytest.mark.parametrize("prec,path,case", [
     ("f32", 1, "fio4096"), ("bf16x3", 1, "fio4096"), ("f32", 1, "synth_L12"),
-    ("f64", 0, "fourier1024"), ("f32", 0, "synth_r8"), ("f32", 0, "grt")])
+    ("f64", 0, "fourier1024"), ("f64", 1, "fio4096"), ("f32", 0, "synth_r8"), ("f32", 0, "grt")])
 def test_noalloc_matches_apply_twice(dev, prec, path, case):
     from paper_1502_01379_amd import BFHandle
     if case == "fio4096":
