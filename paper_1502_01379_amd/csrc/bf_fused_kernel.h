@@ -754,8 +754,9 @@ struct SplitTraits {
   static constexpr int kLdsBytes = 2 * kHB * kBlockBytes + kSwapBytes;
 };
 
-template <int K, int PREC, bool LI, bool LO>
-__global__ __launch_bounds__(BF_SPLIT_MAX_PAIRS * 128) __attribute__((amdgpu_waves_per_eu(4)))
+// CP column chunks (wavefront pairs) per workgroup.
+template <int K, int PREC, bool LI, bool LO, int CP>
+__global__ __launch_bounds__(CP * 128) __attribute__((amdgpu_waves_per_eu(4)))
 void k_fused_pass_x2(FusedArgs a) {
   using T = SplitTraits<K>;
   using G = Geo<16>;
@@ -769,8 +770,8 @@ void k_fused_pass_x2(FusedArgs a) {
   const int n = lane & 15, e = lane >> 4;
   int64_t tile, group;
   tile_of_block(a, tile, group);
-  const int W = (int)(blockDim.x >> 6);  // 2, 4, 8 (or 16) wavefronts
-  const int64_t chunk = group * (W >> 1) + (wave >> 1);
+  constexpr int W = 2 * CP;  // wavefronts
+  const int64_t chunk = group * CP + (wave >> 1);
   const bool active = chunk < a.nchunks;
   const int64_t slo = int64_t(1) << a.log_slo;
   const int64_t hi = tile >> a.log_slo, lo = tile & (slo - 1);
@@ -783,18 +784,22 @@ void k_fused_pass_x2(FusedArgs a) {
   // h PB + i of its buffer, for both halves h.
   __shared__ __attribute__((aligned(16))) char lds[T::kLdsBytes];
   char *const swap = lds + 2 * HB * kBlockBytes;
-  auto issue_stage = [&](int sti) {
+  // every wavefront copies HB lp / W of the stage's 1 KB pieces (W divides HB lp)
+  auto issue_stage = [&](auto STI) {
+    constexpr int sti = STI;
     char *dst = lds + (sti & 1) * (HB * kBlockBytes);
-    const int g = sti / NPART, part = sti % NPART;
-    const int lp = is_leaf_group<K, LI, LO>(g) ? kLeafBytes<16> / 1024 : 8;  // pieces per block
-    for (int c = wave; c < HB * lp; c += W) {
+    constexpr int g = sti / NPART, part = sti % NPART;
+    constexpr int lp = is_leaf_group<K, LI, LO>(g) ? kLeafBytes<16> / 1024 : 8;  // pieces per block
+    static_assert((HB * lp) % W == 0, "pieces per wavefront");
+    static_for<HB * lp / W>([&](auto I) {
+      const int c = wave + (int)I * W;
       const int pos = c / lp, piece = c - pos * lp;
       const int beta = (pos / PB) * WB + part * PB + (pos % PB);
       const float *sp;
       const char *src = group_block<16, K, LI>(a, tile, g, beta, sp) + piece * 1024 + lane * 16;
       __builtin_amdgcn_global_load_lds(
           src, (__attribute__((address_space(3))) void *)(dst + pos * kBlockBytes + piece * 1024), 16, 0, 0);
-    }
+    });
   };
   auto block_scale = [&](int g, int beta) {
     if constexpr (PREC != kF16) return 1.f;
@@ -802,32 +807,38 @@ void k_fused_pass_x2(FusedArgs a) {
     (void)group_block<16, K, LI>(a, tile, g, beta, sp);
     return *sp;
   };
-  issue_stage(0);
+  issue_stage(std::integral_constant<int, 0>{});
 
   float st[HS][SW];
 
-  // ---- inputs at depth 0: tile slots qh .. qh + HS - 1
+  // ---- inputs at depth 0: tile slots qh .. qh + HS - 1, issued in slot order (the
+  // order the first stages take them in)
   static_for<HS>([&](auto J) {
     constexpr int j = J;
+    __builtin_amdgcn_sched_barrier(0);
     const int64_t q = qh + j;
     const int64_t slot = a.mode_si ? base + (q << a.log_slo) + lo : base + (lo << K) + q;
     if constexpr (LI) {
+      // every lane loads (column 0 in place of a missing one), so each wavefront
+      // issues the same number of loads and the first stage can wait for its blocks
+      // alone (stage_begin); the leaf blocks' outputs of missing columns are zeroed
       const f32x2 *g = static_cast<const f32x2 *>(a.in);
+      const int64_t cl = col_ok ? col : 0;
       static_for<NR>([&](auto RHO) {
         constexpr int rho = RHO;
-        f32x2 v = {0.f, 0.f};
-        if (col_ok) v = __builtin_nontemporal_load(&g[(slot * kRank + G::row(e, rho)) * a.ld + col]);
+        const f32x2 v = __builtin_nontemporal_load(&g[(slot * kRank + G::row(e, rho)) * a.ld + cl]);
         st[j][rho] = v.x;
         st[j][NR + rho] = v.y;
       });
     } else {
       const int64_t tr = ((slot & (a.m - 1)) << a.log_m) | (slot >> a.log_m);
       const int64_t src = a.in_kind == kInMiddle ? tr : slot;
-      const f32x4 *p = static_cast<const f32x4 *>(a.in) + ((chunk * a.nslots + src) * 8) * 16 + n;
+      // an idle wavefront pair loads chunk 0 (see above) and stores nothing
+      const int64_t ck = active ? chunk : 0;
+      const f32x4 *p = static_cast<const f32x4 *>(a.in) + ((ck * a.nslots + src) * 8) * 16 + n;
       static_for<NR / 2>([&](auto JJ) {
         constexpr int jj = JJ;
-        f32x4 v = {0.f, 0.f, 0.f, 0.f};
-        if (active) v = __builtin_nontemporal_load(p + G::pair(e, jj) * 16);
+        const f32x4 v = __builtin_nontemporal_load(p + G::pair(e, jj) * 16);
         st[j][2 * jj] = v.x;
         st[j][NR + 2 * jj] = v.y;
         st[j][2 * jj + 1] = v.z;
@@ -868,11 +879,24 @@ void k_fused_pass_x2(FusedArgs a) {
   };
   // entering stage sti: its blocks have landed, every wavefront is done with
   // stage sti - 1, whose buffer now receives stage sti + 1
+  // Barriers are bare s_barriers between explicit waits: a workgroup fence would also
+  // wait for every load in flight.  The empty asm statements keep the compiler from
+  // moving LDS accesses across them.  The first stage waits for its own block copies
+  // only: the state loads issued after them (HS NR / 2, or HS NR from the user vector)
+  // may still be in flight, and each level waits for the slots it takes (loads complete
+  // in order).
+  auto barrier_after = [&](auto VM) {
+    constexpr int vm = VM;
+    __builtin_amdgcn_s_waitcnt((vm & 15) | (7 << 4) | ((vm >> 4) << 14));  // vmcnt(vm) lgkmcnt(0)
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+  };
   auto stage_begin = [&](auto STI) {
     constexpr int sti = STI;
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
-    if constexpr (sti + 1 < NST) issue_stage(sti + 1);
+    constexpr int state_loads = LI ? HS * NR : HS * NR / 2;
+    barrier_after(std::integral_constant<int, sti == 0 ? state_loads : 0>{});
+    if constexpr (sti + 1 < NST) issue_stage(std::integral_constant<int, sti + 1>{});
   };
   // leaf blocks: slots 2 bw, 2 bw + 1 of this half
   auto pair_group = [&](auto GG) {
@@ -882,9 +906,12 @@ void k_fused_pass_x2(FusedArgs a) {
       if constexpr (bw % PB == 0) stage_begin(std::integral_constant<int, g * NPART + bw / PB>{});
       float t0[SW], t1[SW];
       step(GG, BW, st[2 * bw], st[2 * bw + 1], t0, t1);
+      // leaf-in: columns past nrhs (loaded from column 0) become zeros, as every
+      // activation buffer holds there
+      const bool keep = !(LI && g == 0) || col_ok;
       static_for<SW>([&](auto JJ) {
-        st[2 * bw][JJ] = t0[JJ];
-        st[2 * bw + 1][JJ] = t1[JJ];
+        st[2 * bw][JJ] = keep ? t0[JJ] : 0.f;
+        st[2 * bw + 1][JJ] = keep ? t1[JJ] : 0.f;
       });
     });
   };
@@ -941,7 +968,7 @@ void k_fused_pass_x2(FusedArgs a) {
   });
   static_for<T::kRounds>([&](auto R) {
     constexpr int r0 = R * T::kSR;
-    if constexpr (R > 0) __syncthreads();  // the previous round's reads are done
+    if constexpr (R > 0) barrier_after(std::integral_constant<int, 63>{});  // the previous round's reads are done
     static_for<T::kSR>([&](auto S) {
       constexpr int k = r0 + S;
       if constexpr (k < WB) {
@@ -950,7 +977,7 @@ void k_fused_pass_x2(FusedArgs a) {
         w[64] = f32x4{st[k][4], st[k][5], st[k][6], st[k][7]};
       }
     });
-    __syncthreads();
+    barrier_after(std::integral_constant<int, 63>{});  // this round's writes are done
     static_for<T::kSR>([&](auto S) {
       constexpr int k = r0 + S;
       if constexpr (k < WB) {
@@ -1027,14 +1054,22 @@ hipError_t launch_f64(FusedArgs a, int K, bool leaf_in, bool leaf_out, hipStream
                        a);                                                                    \
   } while (0)
 
-#define BF_FUSED_LAUNCH_X2(KK, PREC, LI, LO)                                                  \
-  do {                                                                                        \
-    const int64_t w = a.nchunks >= BF_SPLIT_MAX_PAIRS ? BF_SPLIT_MAX_PAIRS                  \
-                      : a.nchunks >= 4 ? 4 : a.nchunks >= 2 ? 2 : 1;                            \
-    a.ngroups = (int)((a.nchunks + w - 1) / w);                                               \
-    hipLaunchKernelGGL((k_fused_pass_x2<KK, PREC, LI, LO>),                                   \
-                       dim3((unsigned)(a.ntiles * a.ngroups)), dim3((unsigned)(w * 128)), 0, s, \
-                       a);                                                                    \
+template <int K, int PREC, bool LI, bool LO, int CP>
+void launch_x2(FusedArgs a, hipStream_t s) {
+  a.ngroups = (int)((a.nchunks + CP - 1) / CP);
+  hipLaunchKernelGGL((k_fused_pass_x2<K, PREC, LI, LO, CP>), dim3((unsigned)(a.ntiles * a.ngroups)),
+                     dim3((unsigned)(CP * 128)), 0, s, a);
+}
+
+// column chunks per workgroup: the most (up to BF_SPLIT_MAX_PAIRS) that the column count fills
+#define BF_FUSED_LAUNCH_X2(KK, PREC, LI, LO)                                        \
+  do {                                                                              \
+    if (a.nchunks >= BF_SPLIT_MAX_PAIRS)                                            \
+      launch_x2<KK, PREC, LI, LO, BF_SPLIT_MAX_PAIRS>(a, s);                        \
+    else if (a.nchunks >= 2)                                                        \
+      launch_x2<KK, PREC, LI, LO, 2>(a, s);                                         \
+    else                                                                            \
+      launch_x2<KK, PREC, LI, LO, 1>(a, s);                                         \
   } while (0)
 
 #define BF_FUSED_CASES_X2(KK, PREC)                            \
