@@ -199,11 +199,14 @@ void k_fused_pass_f64(FusedArgs a) {
     const int64_t q = qh + j;
     const int64_t slot = a.mode_si ? base + (q << a.log_slo) + lo : base + (lo << K) + q;
     if constexpr (LI) {
+      // every lane loads (column 0 in place of a missing one), so each wavefront
+      // issues the same number of loads and the first stage can wait for its blocks
+      // alone (stage_begin); the leaf blocks' outputs of missing columns are zeroed
       const f64x2 *g = static_cast<const f64x2 *>(a.in);
+      const int64_t cl = col_ok ? col : 0;
       static_for<4>([&](auto RHO) {
         constexpr int rho = RHO;
-        f64x2 v = {0.0, 0.0};
-        if (col_ok) v = __builtin_nontemporal_load(&g[(slot * kRank + 4 * rho + e) * a.ld + col]);
+        const f64x2 v = __builtin_nontemporal_load(&g[(slot * kRank + 4 * rho + e) * a.ld + cl]);
         st[j][rho] = v.x;
         st[j][4 + rho] = v.y;
       });
@@ -211,11 +214,12 @@ void k_fused_pass_f64(FusedArgs a) {
       // the first pass after the middle level reads the transposed slot
       const int64_t tr = ((slot & (a.m - 1)) << a.log_m) | (slot >> a.log_m);
       const int64_t src = a.in_kind == kInMiddle ? tr : slot;
-      const f64x2 *p = static_cast<const f64x2 *>(a.in) + ((chunk * a.nslots + src) * kRank + e) * 16 + n;
+      // an idle wavefront pair loads chunk 0 (see above) and stores nothing
+      const int64_t ck = active ? chunk : 0;
+      const f64x2 *p = static_cast<const f64x2 *>(a.in) + ((ck * a.nslots + src) * kRank + e) * 16 + n;
       static_for<4>([&](auto RHO) {
         constexpr int rho = RHO;
-        f64x2 v = {0.0, 0.0};
-        if (active) v = __builtin_nontemporal_load(p + rho * 64);
+        const f64x2 v = __builtin_nontemporal_load(p + rho * 64);
         st[j][rho] = v.x;
         st[j][4 + rho] = v.y;
       });
@@ -252,13 +256,25 @@ void k_fused_pass_f64(FusedArgs a) {
     else
       block16_f64(blk, lane, x0, x1, y0, y1);
   };
+  // Barriers are bare s_barriers after explicit waits (a workgroup fence would also
+  // wait for every load in flight); the empty asm statements keep the compiler from
+  // moving LDS accesses across them.
+  auto barrier_after = [&](auto VM) {
+    constexpr int vm = VM;
+    static_assert(vm >= 0 && vm <= 63, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt(waitcnt_vm(vm));
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+  };
   // entering stage sti: its blocks have landed (only the loads of the stages after
-  // it may still be in flight; loads complete in order), every wavefront is done
-  // with stage sti - 1, whose buffer now receives stage sti + NBUF - 1
+  // it, and at the first stage the tile's state loads, may still be in flight; loads
+  // complete in order), every wavefront is done with stage sti - 1, whose buffer now
+  // receives stage sti + NBUF - 1
   auto stage_begin = [&](auto STI) {
     constexpr int sti = STI;
-    __builtin_amdgcn_s_waitcnt(waitcnt_vm(pending(sti)));
-    __syncthreads();
+    constexpr int state_loads = HS * 4;
+    barrier_after(std::integral_constant<int, pending(sti) + (sti == 0 ? state_loads : 0)>{});
     if constexpr (sti + NBUF - 1 < NST) issue_stage(std::integral_constant<int, sti + NBUF - 1>{});
   };
   // leaf blocks: slots 2 bw, 2 bw + 1 of this wavefront
@@ -269,9 +285,11 @@ void k_fused_pass_f64(FusedArgs a) {
       stage_begin(std::integral_constant<int, g * WB + bw>{});
       double t0[8], t1[8];
       step(GG, BW, st[2 * bw], st[2 * bw + 1], t0, t1);
+      // leaf-in: columns past nrhs (loaded from column 0) become zeros
+      const bool keep = !(LI && g == 0) || col_ok;
       static_for<8>([&](auto V) {
-        st[2 * bw][V] = t0[V];
-        st[2 * bw + 1][V] = t1[V];
+        st[2 * bw][V] = keep ? t0[V] : 0.0;
+        st[2 * bw + 1][V] = keep ? t1[V] : 0.0;
       });
     });
   };
@@ -315,13 +333,13 @@ void k_fused_pass_f64(FusedArgs a) {
     });
     static_for<WB>([&](auto KK) {
       constexpr int k = KK;
-      if constexpr (k > 0) __syncthreads();  // the previous round's reads are done
+      if constexpr (k > 0) barrier_after(std::integral_constant<int, 63>{});  // the previous round's reads are done
       f64x2 *w = reinterpret_cast<f64x2 *>(swap + wave * T::kSlotBytes) + lane;
       static_for<4>([&](auto I) {
         constexpr int i = I;
         w[64 * i] = f64x2{st[k][2 * i], st[k][2 * i + 1]};
       });
-      __syncthreads();
+      barrier_after(std::integral_constant<int, 63>{});  // this round's writes are done
       const f64x2 *rp = reinterpret_cast<const f64x2 *>(swap + (wave ^ 1) * T::kSlotBytes) + lane;
       static_for<4>([&](auto I) {
         constexpr int i = I;
