@@ -21,11 +21,12 @@
 // (wavefront h holds the tile slots h 2^(K-1) + j), which swap half of their
 // slots through LDS before the last level, as k_fused_pass_x2 does; shallower
 // passes give the tile to one wavefront.  Blocks stream into LDS with
-// global -> LDS loads, one block per wavefront position and stage, one stage
-// ahead.  A workgroup holds up to two column chunks of one tile (80 KB of LDS, so
-// two workgroups share a CU and overlap each other's loads; four chunks per
-// workgroup, one workgroup per CU, were 5% slower at N = 2^20, 256 columns);
-// workgroups of one tile get ids eight apart (same XCD, shared L2).
+// global -> LDS loads, one block (or half block) per wavefront position and stage,
+// one stage (or three half-block stages) ahead.  A workgroup holds up to two column
+// chunks of one tile (80 KB of LDS, so two workgroups share a CU and overlap each
+// other's loads; four chunks per workgroup, one workgroup per CU, were 5% slower at
+// N = 2^20, 256 columns); workgroups of one tile get ids eight apart (same XCD,
+// shared L2).
 #include <hip/hip_runtime.h>
 
 #include "bf_fused_kernel.h"
@@ -42,16 +43,28 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 #ifndef BF_F64_STAGE_BUFFERS
 #define BF_F64_STAGE_BUFFERS 2
 #endif
+// Stages per block: whole blocks through two buffers (PARTS 1), or two halves, one
+// per output tile, through four buffers in the same LDS (PARTS 2: the copies run
+// one and a half blocks ahead).  Measured at N = 2^20, 256 columns, same box and
+// process: halves take the leaf-out pass from 4.34 to 4.19 ms, whole blocks the
+// middle passes from 3.88 to 3.82 ms; leaf-in passes are even.
+#ifndef BF_F64_PARTS
+#define BF_F64_PARTS 1
+#endif
+#ifndef BF_F64_PARTS_LO
+#define BF_F64_PARTS_LO 2
+#endif
 
 // CW column chunks per workgroup; blocks stream through NBUF LDS stage buffers,
 // NBUF - 1 stages ahead of the one being computed.
-template <int K, int CW, int NBUF>
+template <int K, int CW, int NBUF, int PARTS>
 struct F64Traits {
   static constexpr int kW = K >= 3 ? 2 : 1;                 // wavefronts per tile of one chunk
   static constexpr int kHS = (1 << K) / kW;                 // slots per wavefront
   static constexpr int kWB = kHS / 2;                       // blocks per wavefront per level
   static constexpr int kWaves = CW * kW;                    // wavefronts per workgroup
-  static constexpr int kStageBytes = kW * kBlockBytes64;    // one block per wavefront position
+  static constexpr int kParts = PARTS;                      // stages per block (1, or one per output tile)
+  static constexpr int kStageBytes = kW * kBlockBytes64 / kParts;  // a block (part) per wavefront position
   static constexpr int kSlotBytes = 4096;                   // one slot of one wavefront (64 x 8 doubles)
   static constexpr int kSwapBytes = kW == 2 ? kWaves * kSlotBytes : 0;  // one slot per wavefront per round
   static constexpr int kLdsBytes = NBUF * kStageBytes + kSwapBytes;
@@ -70,89 +83,82 @@ __device__ __forceinline__ const char *block64(const FusedArgs &a, int64_t tile,
   return a.fac + (((int64_t)d * a.ntiles + tile) * NB + beta) * (int64_t)kBlockBytes64;
 }
 
-// One 32 x 32 block times the input slots x0 (c' = 0) and x1 (c' = 1).  Packed
-// block: lane i + 16e holds M[16T + i][16c' + 4 rho + e] of K step k = 4c' + rho at
-// double (((2T + part) 4 + k / 2) 64 + lane) 2 + k % 2 (part 0: Re M, 1: Im M).
-// The operands of one output tile are read from LDS just before its products.
-__device__ __forceinline__ void block16_f64(const char *blk, int lane, const double *x0, const double *x1,
-                                            double *y0, double *y1) {
+// One output tile T (rows 16T .. 16T + 15, i.e. output slot T) of a 32 x 32 block
+// times the input slots x0 (c' = 0) and x1 (c' = 1).  Packed block: lane i + 16e holds
+// M[16T + i][16c' + 4 rho + e] of K step k = 4c' + rho at double
+// (((2T + part) 4 + k / 2) 64 + lane) 2 + k % 2 (part 0: Re M, 1: Im M); tile T's
+// operands are the 8 KB at T * 8 KB, passed here as blkT.
+__device__ __forceinline__ void tile16_f64(const char *blkT, int lane, const double *x0, const double *x1,
+                                           double *y) {
+  const f64x2 *bp = reinterpret_cast<const f64x2 *>(blkT) + lane;
+  f64x4 p1 = {}, p2 = {}, p3 = {};
+  // operands of two K steps at a time (the register budget holds the state)
+  f64x2 av = bp[0], bv = bp[256];
 #pragma unroll
-  for (int T = 0; T < 2; ++T) {
-    __builtin_amdgcn_sched_barrier(0);
-    const f64x2 *bp = reinterpret_cast<const f64x2 *>(blk) + T * 512 + lane;
-    f64x4 p1 = {}, p2 = {}, p3 = {};
-    // operands of two K steps at a time (the register budget holds the state)
-    f64x2 av = bp[0], bv = bp[256];
-#pragma unroll
-    for (int kk = 0; kk < 4; ++kk) {
-      f64x2 an = av, bn = bv;
-      if (kk < 3) {
-        an = bp[(kk + 1) * 64];
-        bn = bp[256 + (kk + 1) * 64];
-      }
-#pragma unroll
-      for (int k = 2 * kk; k < 2 * kk + 2; ++k) {
-        const double *x = (k >> 2) ? x1 : x0;
-        const int rho = k & 3;
-        const double xre = x[rho], xim = x[4 + rho];
-        const double am = (k & 1) ? av.y : av.x;
-        const double bm = (k & 1) ? bv.y : bv.x;
-        p1 = __builtin_amdgcn_mfma_f64_16x16x4f64(am, xre, p1, 0, 0, 0);
-        p2 = __builtin_amdgcn_mfma_f64_16x16x4f64(bm, xim, p2, 0, 0, 0);
-        p3 = __builtin_amdgcn_mfma_f64_16x16x4f64(am + bm, xre + xim, p3, 0, 0, 0);
-      }
-      av = an;
-      bv = bn;
+  for (int kk = 0; kk < 4; ++kk) {
+    f64x2 an = av, bn = bv;
+    if (kk < 3) {
+      an = bp[(kk + 1) * 64];
+      bn = bp[256 + (kk + 1) * 64];
     }
-    double *y = T ? y1 : y0;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      y[v] = p1[v] - p2[v];
-      y[4 + v] = p3[v] - p1[v] - p2[v];
-    }
-  }
-}
-
-// A leaf pair: slot c times its own 16 x 16 block M_c.  Packed pair: lane i + 16e
-// holds M_c[i][4 rho + e] at double (((2c + part) 2 + rho / 2) 64 + lane) 2 + rho % 2.
-__device__ __forceinline__ void leaf_pair_f64(const char *blk, int lane, const double *x0, const double *x1,
-                                              double *y0, double *y1) {
-#pragma unroll
-  for (int c = 0; c < 2; ++c) {
-    const f64x2 *bp = reinterpret_cast<const f64x2 *>(blk) + c * 256 + lane;
-    const f64x2 a01 = bp[0], a23 = bp[64], b01 = bp[128], b23 = bp[192];
-    const double *x = c ? x1 : x0;
-    f64x4 p1 = {}, p2 = {}, p3 = {};
-#pragma unroll
-    for (int rho = 0; rho < 4; ++rho) {
-      const f64x2 ap = rho < 2 ? a01 : a23, bp2 = rho < 2 ? b01 : b23;
-      const double am = (rho & 1) ? ap.y : ap.x, bm = (rho & 1) ? bp2.y : bp2.x;
+    for (int k = 2 * kk; k < 2 * kk + 2; ++k) {
+      const double *x = (k >> 2) ? x1 : x0;
+      const int rho = k & 3;
       const double xre = x[rho], xim = x[4 + rho];
+      const double am = (k & 1) ? av.y : av.x;
+      const double bm = (k & 1) ? bv.y : bv.x;
       p1 = __builtin_amdgcn_mfma_f64_16x16x4f64(am, xre, p1, 0, 0, 0);
       p2 = __builtin_amdgcn_mfma_f64_16x16x4f64(bm, xim, p2, 0, 0, 0);
       p3 = __builtin_amdgcn_mfma_f64_16x16x4f64(am + bm, xre + xim, p3, 0, 0, 0);
     }
-    double *y = c ? y1 : y0;
+    av = an;
+    bv = bn;
+  }
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      y[v] = p1[v] - p2[v];
-      y[4 + v] = p3[v] - p1[v] - p2[v];
-    }
+  for (int v = 0; v < 4; ++v) {
+    y[v] = p1[v] - p2[v];
+    y[4 + v] = p3[v] - p1[v] - p2[v];
+  }
+}
+
+// A leaf pair: slot c times its own 16 x 16 block M_c.  Packed pair: lane i + 16e
+// holds M_c[i][4 rho + e] at double (((2c + part) 2 + rho / 2) 64 + lane) 2 + rho % 2;
+// slot c's operands are the 4 KB at c * 4 KB, passed here as blkc.
+__device__ __forceinline__ void leaf16_f64(const char *blkc, int lane, const double *x, double *y) {
+  const f64x2 *bp = reinterpret_cast<const f64x2 *>(blkc) + lane;
+  const f64x2 a01 = bp[0], a23 = bp[64], b01 = bp[128], b23 = bp[192];
+  f64x4 p1 = {}, p2 = {}, p3 = {};
+#pragma unroll
+  for (int rho = 0; rho < 4; ++rho) {
+    const f64x2 ap = rho < 2 ? a01 : a23, bp2 = rho < 2 ? b01 : b23;
+    const double am = (rho & 1) ? ap.y : ap.x, bm = (rho & 1) ? bp2.y : bp2.x;
+    const double xre = x[rho], xim = x[4 + rho];
+    p1 = __builtin_amdgcn_mfma_f64_16x16x4f64(am, xre, p1, 0, 0, 0);
+    p2 = __builtin_amdgcn_mfma_f64_16x16x4f64(bm, xim, p2, 0, 0, 0);
+    p3 = __builtin_amdgcn_mfma_f64_16x16x4f64(am + bm, xre + xim, p3, 0, 0, 0);
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    y[v] = p1[v] - p2[v];
+    y[4 + v] = p3[v] - p1[v] - p2[v];
   }
 }
 
 // Activations (FP64): [chunk][slot][row 16][column 16] complex128; user vectors
 // g, u: [N][ld] complex128.
-template <int K, bool LI, bool LO, int CW, int NBUF>
-__global__ __launch_bounds__((F64Traits<K, CW, NBUF>::kWaves * 64)) __attribute__((amdgpu_waves_per_eu(2)))
+template <int K, bool LI, bool LO, int CW, int NBUF, int PARTS>
+__global__ __launch_bounds__((F64Traits<K, CW, NBUF, PARTS>::kWaves * 64)) __attribute__((amdgpu_waves_per_eu(2)))
 void k_fused_pass_f64(FusedArgs a) {
-  using T = F64Traits<K, CW, NBUF>;
+  using T = F64Traits<K, CW, NBUF, PARTS>;
   constexpr int W = T::kW, HS = T::kHS, WB = T::kWB, NW = T::kWaves;
-  constexpr int NST = ((LI ? 1 : 0) + K + (LO ? 1 : 0)) * WB;
+  constexpr int NST = ((LI ? 1 : 0) + K + (LO ? 1 : 0)) * WB * PARTS;
   // global -> LDS loads of one wavefront for stage s (16 or 8 pieces of 1 KB per
-  // block, spread over the workgroup's NW wavefronts), and those of the stages
-  // after sti that are in flight when stage sti begins
-  constexpr auto loads_of = [](int s) { return (is_leaf_group<K, LI, LO>(s / WB) ? 8 : 16) * W / NW; };
+  // block, over PARTS stages, spread over the workgroup's NW wavefronts), and those of
+  // the stages after sti that are in flight when stage sti begins
+  constexpr auto loads_of = [](int s) {
+    return (is_leaf_group<K, LI, LO>(s / (WB * PARTS)) ? 8 : 16) / PARTS * W / NW;
+  };
   constexpr auto pending = [loads_of](int sti) {
     int n = 0;
     for (int s = sti + 1; s <= sti + NBUF - 2 && s < NST; ++s) n += loads_of(s);
@@ -179,17 +185,23 @@ void k_fused_pass_f64(FusedArgs a) {
   auto issue_stage = [&](auto STI) {
     constexpr int sti = STI;
     char *dst = lds + (sti % NBUF) * T::kStageBytes;
-    constexpr int g = sti / WB, bw = sti % WB;
-    constexpr int lp = is_leaf_group<K, LI, LO>(g) ? kLeafBytes64 / 1024 : kBlockBytes64 / 1024;
+    constexpr int bs = sti / PARTS, part = sti % PARTS;
+    constexpr int g = bs / WB, bw = bs % WB;
+    constexpr int pbytes = (is_leaf_group<K, LI, LO>(g) ? kLeafBytes64 : kBlockBytes64) / PARTS;
+    constexpr int lp = pbytes / 1024;  // pieces per position
     static_for<loads_of(sti)>([&](auto I) {
       const int c = wave + (int)I * NW;
       const int pos = c / lp, piece = c - pos * lp;
-      const char *src = block64<K, LI>(a, tile, g, pos * WB + bw) + piece * 1024 + lane * 16;
+      const char *src = block64<K, LI>(a, tile, g, pos * WB + bw) + part * pbytes + piece * 1024 + lane * 16;
       __builtin_amdgcn_global_load_lds(
-          src, (__attribute__((address_space(3))) void *)(dst + pos * kBlockBytes64 + piece * 1024), 16, 0, 0);
+          src, (__attribute__((address_space(3))) void *)(dst + pos * (kBlockBytes64 / PARTS) + piece * 1024),
+          16, 0, 0);
     });
   };
   issue_stage(std::integral_constant<int, 0>{});
+  // the counted waits below assume this issue order (first stage, state loads, later
+  // stages): the empty asm statements keep the compiler from interleaving them
+  asm volatile("" ::: "memory");
 
   double st[HS][8];
 
@@ -242,20 +254,11 @@ void k_fused_pass_f64(FusedArgs a) {
   }
   // the next NBUF - 2 stages follow the state loads, so the first stage's wait
   // leaves them in flight
+  asm volatile("" ::: "memory");
   static_for<NBUF - 2>([&](auto I) {
     if constexpr (1 + (int)I < NST) issue_stage(std::integral_constant<int, 1 + (int)I>{});
   });
 
-  // block half WB + bw of group g, staged in LDS
-  auto step = [&](auto GG, auto BW, const double *x0, const double *x1, double *y0, double *y1) {
-    constexpr int g = GG, bw = BW;
-    constexpr int sti = g * WB + bw;
-    const char *blk = lds + (sti % NBUF) * T::kStageBytes + half * kBlockBytes64;
-    if constexpr (is_leaf_group<K, LI, LO>(g))
-      leaf_pair_f64(blk, lane, x0, x1, y0, y1);
-    else
-      block16_f64(blk, lane, x0, x1, y0, y1);
-  };
   // Barriers are bare s_barriers after explicit waits (a workgroup fence would also
   // wait for every load in flight); the empty asm statements keep the compiler from
   // moving LDS accesses across them.
@@ -277,14 +280,33 @@ void k_fused_pass_f64(FusedArgs a) {
     barrier_after(std::integral_constant<int, pending(sti) + (sti == 0 ? state_loads : 0)>{});
     if constexpr (sti + NBUF - 1 < NST) issue_stage(std::integral_constant<int, sti + NBUF - 1>{});
   };
+  // block half WB + bw of group g, staged in LDS (one stage per block, or one per
+  // output slot with PARTS = 2), applied to x0, x1
+  auto butterfly = [&](auto GG, auto BW, const double *x0, const double *x1, double *y0, double *y1) {
+    constexpr int g = GG, bw = BW;
+    constexpr int bs = g * WB + bw;
+    constexpr bool leaf = is_leaf_group<K, LI, LO>(g);
+    static_for<PARTS>([&](auto P) {
+      constexpr int part = P;
+      stage_begin(std::integral_constant<int, bs * PARTS + part>{});
+      const char *pb = lds + ((bs * PARTS + part) % NBUF) * T::kStageBytes + half * (kBlockBytes64 / PARTS);
+      static_for<2 / PARTS>([&](auto Q) {
+        constexpr int c = part + Q;  // output slot (tile) of this part
+        const char *cb = pb + (int)Q * (leaf ? kLeafBytes64 : kBlockBytes64) / 2;
+        if constexpr (leaf)
+          leaf16_f64(cb, lane, c ? x1 : x0, c ? y1 : y0);
+        else
+          tile16_f64(cb, lane, x0, x1, c ? y1 : y0);
+      });
+    });
+  };
   // leaf blocks: slots 2 bw, 2 bw + 1 of this wavefront
   auto pair_group = [&](auto GG) {
     constexpr int g = GG;
     static_for<WB>([&](auto BW) {
       constexpr int bw = BW;
-      stage_begin(std::integral_constant<int, g * WB + bw>{});
       double t0[8], t1[8];
-      step(GG, BW, st[2 * bw], st[2 * bw + 1], t0, t1);
+      butterfly(GG, BW, st[2 * bw], st[2 * bw + 1], t0, t1);
       // leaf-in: columns past nrhs (loaded from column 0) become zeros
       const bool keep = !(LI && g == 0) || col_ok;
       static_for<8>([&](auto V) {
@@ -304,11 +326,10 @@ void k_fused_pass_f64(FusedArgs a) {
     double nx[HS][8];
     static_for<WB>([&](auto BW) {
       constexpr int bw = BW;
-      stage_begin(std::integral_constant<int, g * WB + bw>{});
       constexpr int ap = bw >> d, b = bw & ((1 << d) - 1);
       constexpr int qi0 = (2 * ap) * (1 << d) + b, qi1 = qi0 + (1 << d);
       constexpr int qo0 = ap * (2 << d) + 2 * b, qo1 = qo0 + 1;
-      step(std::integral_constant<int, g>{}, BW, st[qi0], st[qi1], nx[qo0], nx[qo1]);
+      butterfly(std::integral_constant<int, g>{}, BW, st[qi0], st[qi1], nx[qo0], nx[qo1]);
     });
     static_for<HS>([&](auto Q) {
       static_for<8>([&](auto V) { st[Q][V] = nx[Q][V]; });
@@ -350,13 +371,12 @@ void k_fused_pass_f64(FusedArgs a) {
     });
     static_for<WB>([&](auto KK) {
       constexpr int k = KK;
-      stage_begin(std::integral_constant<int, gl * WB + k>{});
       double x0[8], x1[8];
       static_for<8>([&](auto V) {
         x0[V] = half ? rv[k][V] : kp[k][V];
         x1[V] = half ? kp[k][V] : rv[k][V];
       });
-      step(std::integral_constant<int, gl>{}, KK, x0, x1, st[2 * k], st[2 * k + 1]);
+      butterfly(std::integral_constant<int, gl>{}, KK, x0, x1, st[2 * k], st[2 * k + 1]);
     });
   }
 
@@ -390,10 +410,11 @@ void k_fused_pass_f64(FusedArgs a) {
 
 template <int K, bool LI, bool LO, int CW>
 void launch_f64_cw(FusedArgs a, hipStream_t s) {
-  constexpr int NBUF = CW >= 4 ? BF_F64_STAGE_BUFFERS : 2;
-  using T = F64Traits<K, CW, NBUF>;
+  constexpr int PARTS = LO ? BF_F64_PARTS_LO : BF_F64_PARTS;
+  constexpr int NBUF = PARTS == 2 ? 4 : CW >= 4 ? BF_F64_STAGE_BUFFERS : 2;
+  using T = F64Traits<K, CW, NBUF, PARTS>;
   a.ngroups = (int)((a.nchunks + CW - 1) / CW);
-  hipLaunchKernelGGL((k_fused_pass_f64<K, LI, LO, CW, NBUF>), dim3((unsigned)(a.ntiles * a.ngroups)),
+  hipLaunchKernelGGL((k_fused_pass_f64<K, LI, LO, CW, NBUF, PARTS>), dim3((unsigned)(a.ntiles * a.ngroups)),
                      dim3((unsigned)(T::kWaves * 64)), 0, s, a);
 }
 
