@@ -368,14 +368,14 @@ def cpu_oracle_baseline(f, g_host, sample, kern_rows, N):
     return base, ref
 
 
-def profile_traffic(key):
+def profile_traffic(key, source="bf_fused_kernel.h"):
     """HBM bytes per launch of one pass kernel from the committed rocprofv3 counter
     summaries (FETCH_SIZE and WRITE_SIZE, scaled by a copy kernel of known size),
-    or None when no summary covers it or the kernel source changed since."""
+    or None when no summary covers it or the kernel's source file changed since."""
     import glob
     import hashlib
     here = os.path.dirname(os.path.abspath(__file__))
-    src = os.path.join(here, "paper_1502_01379_amd", "csrc", "bf_fused_kernel.h")
+    src = os.path.join(here, "paper_1502_01379_amd", "csrc", source)
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
     for path in sorted(glob.glob(os.path.join(here, "profiles", "*.txt"))):
         for line in open(path):
@@ -482,7 +482,8 @@ def main():
                 "peak": HBM_PEAK_GBS, "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
     prec_code = {"f32": 0, "bf16x3": 1, "f16x3": 2, "f64": 3}[args.precision]
-    roof["traffic"] = profile_traffic(f"{K},{prec_code},{int(reads_g)},{int(writes_u)}")
+    roof["traffic"] = profile_traffic(f"{K},{prec_code},{int(reads_g)},{int(writes_u)}",
+                                      "bf_fused_f64.hip" if args.precision == "f64" else "bf_fused_kernel.h")
     roof["kernel"] = name
     roof["avg_launch_ms"] = avg_ms
     roof["launches"] = launches
