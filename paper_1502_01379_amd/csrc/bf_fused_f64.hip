@@ -179,8 +179,8 @@ void k_fused_pass_f64(FusedArgs a) {
   const bool col_ok = active && col < a.nrhs;
   const int qh = half * HS;  // first tile slot of this wavefront
 
-  // stage sti = (group g, block bw): block half WB + bw of group g for both halves,
-  // at position half of LDS buffer sti % NBUF
+  // stage sti = (group g, block bw, part): that part of block half WB + bw of group g
+  // for both halves, at position half of LDS buffer sti % NBUF
   __shared__ __attribute__((aligned(16))) char lds[T::kLdsBytes];
   auto issue_stage = [&](auto STI) {
     constexpr int sti = STI;
