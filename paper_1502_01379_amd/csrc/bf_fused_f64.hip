@@ -270,14 +270,25 @@ void k_fused_pass_f64(FusedArgs a) {
     __builtin_amdgcn_s_barrier();
     asm volatile("" ::: "memory");
   };
-  // entering stage sti: its blocks have landed (only the loads of the stages after
-  // it, and at the first stage the tile's state loads, may still be in flight; loads
-  // complete in order), every wavefront is done with stage sti - 1, whose buffer now
-  // receives stage sti + NBUF - 1
+  // entering stage sti: its blocks have landed (only the copies of the stages after it
+  // may still be in flight; loads complete in order), every wavefront is done with
+  // stage sti - 1, whose buffer now receives stage sti + NBUF - 1.  The first stage
+  // also waits for the tile's state loads, and the empty asm statements after it keep
+  // the compiler from moving work on the state above the barrier: a wait of the
+  // compiler's own for a state register, with block copies in flight, would be a full
+  // vmcnt(0) and drain the copies of the next stages (N = 2^20, 256 columns: 16.17-16.21
+  // -> 16.06-16.09 ms per apply)
   auto stage_begin = [&](auto STI) {
     constexpr int sti = STI;
-    constexpr int state_loads = HS * 4;
-    barrier_after(std::integral_constant<int, pending(sti) + (sti == 0 ? state_loads : 0)>{});
+    barrier_after(std::integral_constant<int, pending(sti)>{});
+    if constexpr (sti == 0) {
+      static_for<HS>([&](auto J) {
+        static_for<8>([&](auto V) {
+          double &x = st[(int)J][(int)V];
+          asm volatile("" : "+v"(x));
+        });
+      });
+    }
     if constexpr (sti + NBUF - 1 < NST) issue_stage(std::integral_constant<int, sti + NBUF - 1>{});
   };
   // block half WB + bw of group g, staged in LDS (one stage per block, or one per

@@ -124,3 +124,97 @@ def test_pair_tile_first_stage_copies_complete_at_first_barrier(asm, prec):
         assert not late, f"K={K} LI={li} LO={lo} CP={cp}: first-stage copies {late} outstanding ({orders})"
         seen += 1
     assert seen >= 12
+
+
+def _barrier_model(K, li, lo, wb, parts, copies, two_waves):
+    """Per-wavefront copies of each stage and the kinds of the barriers in program
+    order (a stage index, or None for the barriers of the half-swap before the last
+    level), for a pass of K levels with wb blocks per wavefront per level."""
+    groups = (1 if li else 0) + K + (1 if lo else 0)
+    per_group = wb * parts
+    nst = groups * per_group
+    cps = [copies(s // per_group in ((0,) if li else ()) or (lo and s // per_group == groups - 1)) for s in range(nst)]
+    if not two_waves:
+        return cps, list(range(nst))
+    gl = (1 if li else 0) + K - 1  # group of the last level, entered after the swap
+    return cps, list(range(gl * per_group)) + [None] * (2 * wb - 1) + list(range(gl * per_group, nst))
+
+
+def _replay_stages(lines, cps, barriers):
+    """Walk every path from the kernel entry to its end; at each stage barrier no copy
+    of that stage or an earlier one may be outstanding.  Returns the violations and the
+    (barriers, copies) counts seen at the end of each path."""
+    stage = [s for s, c in enumerate(cps) for _ in range(c)]
+    ins = [l.strip() for l in lines]
+    labels = {s[:-1]: i for i, s in enumerate(ins) if re.match(r"^\.LBB\w+:$", s)}
+    bad, ends, seen = set(), set(), set()
+    work = [(0, (), 0, 0)]
+    while work:
+        i, outstanding, ncopy, nbar = work.pop()
+        while True:
+            key = (i, outstanding, ncopy, nbar)
+            if key in seen:
+                break
+            seen.add(key)
+            s = ins[i]
+            if s.startswith("s_endpgm"):
+                ends.add((nbar, ncopy))
+                break
+            if s.startswith("s_barrier"):
+                kind = barriers[nbar] if nbar < len(barriers) else "extra"
+                if kind == "extra":
+                    bad.add(("extra barrier", nbar))
+                elif kind is not None:
+                    late = [stage[c] for c in outstanding if c >= 0 and stage[c] <= kind]
+                    if late:
+                        bad.add((kind, tuple(sorted(set(late)))))
+                nbar += 1
+            elif s.startswith("global_load"):
+                if s.startswith("global_load_lds"):
+                    assert ncopy < len(stage), "more copies than the pass structure issues"
+                    outstanding, ncopy = outstanding + (ncopy,), ncopy + 1
+                else:
+                    outstanding = outstanding + (-1,)
+            elif s.startswith("s_waitcnt") and "vmcnt" in s:
+                n = int(re.search(r"vmcnt\((\d+)\)", s).group(1))
+                outstanding = outstanding[max(0, len(outstanding) - n):]
+            elif s.startswith("s_branch"):
+                i = labels[s.split()[1]]
+                continue
+            elif s.startswith("s_cbranch"):
+                work.append((labels[s.split()[1]], outstanding, ncopy, nbar))
+            i += 1
+    return bad, ends
+
+
+def test_f64_every_stage_copies_complete_at_its_barrier(asm):
+    checked = 0
+    pattern = r"k_fused_pass_f64ILi(\d)ELb(\d)ELb(\d)ELi(\d)ELi(\d)ELi(\d)E"
+    for (K, li, lo, cw, nbuf, parts), lines in _kernels(asm["f64"], pattern):
+        w = 2 if K >= 3 else 1
+        if w * cw == 1:
+            continue  # one wavefront per workgroup: no barriers (the first-stage test covers it)
+        wb = (1 << K) // w // 2
+        cps, barriers = _barrier_model(K, li, lo, wb, parts,
+                                       lambda leaf: (8 if leaf else 16) // parts * w // (w * cw), w == 2)
+        bad, ends = _replay_stages(lines, cps, barriers)
+        assert not bad, f"K={K} LI={li} LO={lo} CW={cw}: {sorted(bad)[:4]}"
+        assert ends == {(len(barriers), sum(cps))}, (K, li, lo, cw, ends, len(barriers), sum(cps))
+        checked += 1
+    assert checked == 18
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+def test_pair_tile_every_stage_copies_complete_at_its_barrier(asm, prec):
+    pb = _define(os.path.join(CSRC, "bf_fused_kernel.h"), "BF_SPLIT_PB")
+    checked = 0
+    for (K, p, li, lo, cp), lines in _kernels(asm[prec], r"k_fused_pass_x2ILi(\d)ELi(\d)ELb(\d)ELb(\d)ELi(\d)E"):
+        wb = (1 << (K - 1)) // 2
+        pbk = min(wb, pb)
+        cps, barriers = _barrier_model(K, li, lo, wb // pbk, 1,
+                                       lambda leaf: 2 * pbk * (4 if leaf else 8) // (2 * cp), True)
+        bad, ends = _replay_stages(lines, cps, barriers)
+        assert not bad, f"K={K} LI={li} LO={lo} CP={cp}: {sorted(bad)[:4]}"
+        assert ends == {(len(barriers), sum(cps))}, (K, li, lo, cp, ends, len(barriers), sum(cps))
+        checked += 1
+    assert checked >= 12
