@@ -66,7 +66,9 @@ struct F64Traits {
   static constexpr int kParts = PARTS;                      // stages per block (1, or one per output tile)
   static constexpr int kStageBytes = kW * kBlockBytes64 / kParts;  // a block (part) per wavefront position
   static constexpr int kSlotBytes = 4096;                   // one slot of one wavefront (64 x 8 doubles)
-  static constexpr int kSwapBytes = kW == 2 ? kWaves * kSlotBytes : 0;  // one slot per wavefront per round
+  // the half-swap region (one slot per wavefront per round) also stages the middle
+  // weights of each wavefront's slots (1 KB per wavefront) before the first level
+  static constexpr int kSwapBytes = kW == 2 ? kWaves * kSlotBytes : kWaves * 1024;
   static constexpr int kLdsBytes = NBUF * kStageBytes + kSwapBytes;
 };
 
@@ -199,8 +201,21 @@ void k_fused_pass_f64(FusedArgs a) {
     });
   };
   issue_stage(std::integral_constant<int, 0>{});
-  // the counted waits below assume this issue order (first stage, state loads, later
-  // stages): the empty asm statements keep the compiler from interleaving them
+  // middle weights S^h_{i,j} (real, natural slot order) of this wavefront's slots, into
+  // its 1 KB of the swap region: lane l copies 16 bytes of slot l / 8 (a whole slot row
+  // of 16 values per 8 lanes); applied to the state after the first stage's barrier
+  const bool mid = !LI && a.in_kind == kInMiddle;
+  char *const sreg = lds + NBUF * T::kStageBytes + wave * 1024;
+  if (mid) {
+    const int j = (lane >> 3) < HS ? (lane >> 3) : 0;
+    const int64_t q = qh + j;
+    const int64_t slot = a.mode_si ? base + (q << a.log_slo) + lo : base + (lo << K) + q;
+    const char *src = reinterpret_cast<const char *>(a.Sm64 + slot * kRank) + (lane & 7) * 16;
+    __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)sreg, 16, 0, 0);
+  }
+  // the counted waits below assume this issue order (first stage and middle weights,
+  // state loads, later stages): the empty asm statements keep the compiler from
+  // interleaving them
   asm volatile("" ::: "memory");
 
   double st[HS][8];
@@ -237,21 +252,6 @@ void k_fused_pass_f64(FusedArgs a) {
       });
     }
   });
-  // middle weights S^h_{i,j} (real), in natural slot order
-  if (!LI && a.in_kind == kInMiddle) {
-    static_for<HS>([&](auto J) {
-      constexpr int j = J;
-      const int64_t q = qh + j;
-      const int64_t slot = a.mode_si ? base + (q << a.log_slo) + lo : base + (lo << K) + q;
-      const double *sp = a.Sm64 + slot * kRank + e;
-      static_for<4>([&](auto RHO) {
-        constexpr int rho = RHO;
-        const double sc = sp[4 * rho];
-        st[j][rho] *= sc;
-        st[j][4 + rho] *= sc;
-      });
-    });
-  }
   // the next NBUF - 2 stages follow the state loads, so the first stage's wait
   // leaves them in flight
   asm volatile("" ::: "memory");
@@ -288,6 +288,18 @@ void k_fused_pass_f64(FusedArgs a) {
           asm volatile("" : "+v"(x));
         });
       });
+      // the middle weights landed with the first stage (they were issued before the
+      // state loads); read before the next copy is issued, so no copy is in flight
+      // that the reads could be taken to depend on
+      if (!LI && mid) {
+        static_for<HS>([&](auto J) {
+          static_for<4>([&](auto RHO) {
+            const double sc = *reinterpret_cast<const double *>(sreg + (int)J * 128 + (4 * (int)RHO + e) * 8);
+            st[J][RHO] *= sc;
+            st[J][4 + RHO] *= sc;
+          });
+        });
+      }
     }
     if constexpr (sti + NBUF - 1 < NST) issue_stage(std::integral_constant<int, sti + NBUF - 1>{});
   };
