@@ -652,8 +652,10 @@ hipError_t fused_run_pass(const bf_plan *p, const FusedPass *fp, const void *in,
   if (lvl)
     for (int d = 0; d <= fp->K; ++d) a.lvl[d] = lvl[d];
   const bool li = fp->in_kind == kInUser, lo = fp->out_kind == kOutUser;
-  if (p->bwd_bf16) return launch_prec<kBF16>(a, fp->cols, fp->K, li, lo, fp->split, s);
-  return launch_prec<kF32>(a, fp->cols, fp->K, li, lo, fp->split, s);
+  // a recomputation wants only the states strictly inside the pass
+  const bool inner_only = !out && !lo && lvl && !lvl[fp->K];
+  if (p->bwd_bf16) return launch_prec<kBF16>(a, fp->cols, fp->K, li, lo, fp->split, s, inner_only);
+  return launch_prec<kF32>(a, fp->cols, fp->K, li, lo, fp->split, s, inner_only);
 }
 
 void fused_free(FusedPass *fp) {

@@ -763,7 +763,7 @@ struct SplitTraits {
 };
 
 // CP column chunks (wavefront pairs) per workgroup.
-template <int K, int PREC, bool LI, bool LO, int CP>
+template <int K, int PREC, bool LI, bool LO, int CP, bool IO = false>
 __global__ __launch_bounds__(CP * 128) __attribute__((amdgpu_waves_per_eu(4)))
 void k_fused_pass_x2(FusedArgs a) {
   using T = SplitTraits<K>;
@@ -978,6 +978,13 @@ void k_fused_pass_x2(FusedArgs a) {
     store_depth(d + 1);
   });
 
+  // a pass run only for the states inside it has stored them all; it ends once the
+  // block copies still in flight have landed (none may land after the workgroup)
+  if constexpr (IO) {
+    __builtin_amdgcn_s_waitcnt((7 << 4) | (15 << 8));  // vmcnt(0)
+    return;
+  }
+
   // ---- swap halves through the swap region: kp[k] is the operand this
   // wavefront keeps for block half WB + k, rv[k] the one it receives
   constexpr int gl = (LI ? 1 : 0) + K - 1;  // group of the last level
@@ -1062,10 +1069,13 @@ inline int64_t waves_per_group(const FusedArgs &a) {
   return a.nchunks < mw ? a.nchunks : mw;
 }
 
-// Launch one pass (defined in bf_fused_<prec>.hip).
+// Launch one pass (defined in bf_fused_<prec>.hip).  inner_only: the pass runs only
+// for its per-depth copies strictly inside it (no output, no copy after its last
+// level); the passes with two wavefronts per tile then launch a variant that ends
+// after the levels each wavefront holds on its own.
 template <int PREC>
 hipError_t launch_prec(FusedArgs a, int cols, int K, bool leaf_in, bool leaf_out, bool split,
-                       hipStream_t s);
+                       hipStream_t s, bool inner_only = false);
 // Launch one FP64 pass (bf_fused_f64.hip; 16 columns per wavefront, K <= 4).
 hipError_t launch_f64(FusedArgs a, int K, bool leaf_in, bool leaf_out, hipStream_t s);
 
@@ -1078,33 +1088,40 @@ hipError_t launch_f64(FusedArgs a, int K, bool leaf_in, bool leaf_out, hipStream
                        a);                                                                    \
   } while (0)
 
-template <int K, int PREC, bool LI, bool LO, int CP>
+template <int K, int PREC, bool LI, bool LO, int CP, bool IO>
 void launch_x2(FusedArgs a, hipStream_t s) {
   a.ngroups = (int)((a.nchunks + CP - 1) / CP);
-  hipLaunchKernelGGL((k_fused_pass_x2<K, PREC, LI, LO, CP>), dim3((unsigned)(a.ntiles * a.ngroups)),
+  hipLaunchKernelGGL((k_fused_pass_x2<K, PREC, LI, LO, CP, IO>), dim3((unsigned)(a.ntiles * a.ngroups)),
                      dim3((unsigned)(CP * 128)), 0, s, a);
 }
 
 // column chunks per workgroup: the most (up to BF_SPLIT_MAX_PAIRS) that the column count fills
-#define BF_FUSED_LAUNCH_X2(KK, PREC, LI, LO)                                        \
+#define BF_FUSED_LAUNCH_X2(KK, PREC, LI, LO, IO)                                    \
   do {                                                                              \
     if (a.nchunks >= BF_SPLIT_MAX_PAIRS)                                            \
-      launch_x2<KK, PREC, LI, LO, BF_SPLIT_MAX_PAIRS>(a, s);                        \
+      launch_x2<KK, PREC, LI, LO, BF_SPLIT_MAX_PAIRS, IO>(a, s);                    \
     else if (a.nchunks >= 2)                                                        \
-      launch_x2<KK, PREC, LI, LO, 2>(a, s);                                         \
+      launch_x2<KK, PREC, LI, LO, 2, IO>(a, s);                                     \
     else                                                                            \
-      launch_x2<KK, PREC, LI, LO, 1>(a, s);                                         \
+      launch_x2<KK, PREC, LI, LO, 1, IO>(a, s);                                     \
   } while (0)
 
+// keys 256 + ...: full passes; 512 + ...: passes run only for their inner states
 #define BF_FUSED_CASES_X2(KK, PREC)                            \
   case 256 + KK * 4 + 0:                                       \
-    BF_FUSED_LAUNCH_X2(KK, PREC, false, false);                \
+    BF_FUSED_LAUNCH_X2(KK, PREC, false, false, false);         \
     break;                                                     \
   case 256 + KK * 4 + 2:                                       \
-    BF_FUSED_LAUNCH_X2(KK, PREC, true, false);                 \
+    BF_FUSED_LAUNCH_X2(KK, PREC, true, false, false);          \
     break;                                                     \
   case 256 + KK * 4 + 1:                                       \
-    BF_FUSED_LAUNCH_X2(KK, PREC, false, true);                 \
+    BF_FUSED_LAUNCH_X2(KK, PREC, false, true, false);          \
+    break;                                                     \
+  case 512 + KK * 4 + 0:                                       \
+    BF_FUSED_LAUNCH_X2(KK, PREC, false, false, true);          \
+    break;                                                     \
+  case 512 + KK * 4 + 2:                                       \
+    BF_FUSED_LAUNCH_X2(KK, PREC, true, false, true);           \
     break;
 
 #define BF_FUSED_CASES(COLS, KK, PREC)                         \
@@ -1121,8 +1138,8 @@ void launch_x2(FusedArgs a, hipStream_t s) {
 #define BF_FUSED_DEFINE_LAUNCH(PREC)                                                        \
   template <>                                                                               \
   hipError_t launch_prec<PREC>(FusedArgs a, int cols, int K, bool li, bool lo, bool split, \
-                               hipStream_t s) {                                             \
-    const int key = split && cols == 16 ? 256 : (cols / 16) * 64;                           \
+                               hipStream_t s, bool inner_only) {                            \
+    const int key = split && cols == 16 ? (inner_only && !lo ? 512 : 256) : (cols / 16) * 64; \
     switch (key + K * 4 + (li ? 2 : 0) + (lo ? 1 : 0)) {                                    \
       BF_FUSED_CASES(32, 1, PREC)                                                           \
       BF_FUSED_CASES(32, 2, PREC)                                                           \
